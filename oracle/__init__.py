@@ -1,0 +1,152 @@
+"""FP64 CPU oracle for the shiftable bilateral filter (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library neither imports
+nor links anything here, and nothing here imports the product package.
+
+The C source (``bsk_oracle.c``) evaluates eq. (3) of the paper directly with a
+box spatial window and the rescaled raised-cosine range kernel of eq. (6),
+cos^N(t / (sigma_r sqrt N)); see its header for the definitions.  This module
+only marshals NumPy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bsk_oracle.c")
+_LIB = os.path.join(_HERE, "_liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_llp = ctypes.POINTER(ctypes.c_longlong)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-D_DEFAULT_SOURCE", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    lib.oracle_order_for.restype = ctypes.c_int
+    lib.oracle_order_for.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.oracle_kernel.restype = ctypes.c_double
+    lib.oracle_kernel.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_kernel_deriv.restype = ctypes.c_double
+    lib.oracle_kernel_deriv.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_trunc_terms.restype = ctypes.c_int
+    lib.oracle_trunc_terms.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+    lib.oracle_trunc_kernel.restype = ctypes.c_double
+    lib.oracle_trunc_kernel.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    lib.oracle_bilateral_f64.restype = None
+    lib.oracle_bilateral_f64.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_bilateral.restype = None
+    lib.oracle_bilateral.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_bilateral_at.restype = None
+    lib.oracle_bilateral_at.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_int, _llp, ctypes.c_longlong,
+                                        _dp, _dp, _dp]
+    lib.oracle_bilateral_grad_f64.restype = None
+    lib.oracle_bilateral_grad_f64.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def order_for(sigma_r: float, T: float) -> int:
+    """N_0: the smallest order keeping the kernel non-negative and unimodal on [-T, T]."""
+    return _load().oracle_order_for(float(sigma_r), float(T))
+
+
+def kernel(t: float, sigma_r: float, N: int) -> float:
+    return _load().oracle_kernel(float(t), float(sigma_r), int(N))
+
+
+def kernel_deriv(t: float, sigma_r: float, N: int) -> float:
+    return _load().oracle_kernel_deriv(float(t), float(sigma_r), int(N))
+
+
+def trunc_terms(N: int, eps: float):
+    """(number of kept terms, dropped weight mass) for truncation threshold eps."""
+    d = ctypes.c_double(0.0)
+    kept = _load().oracle_trunc_terms(int(N), float(eps), ctypes.byref(d))
+    return kept, d.value
+
+
+def trunc_kernel(t: float, sigma_r: float, N: int, eps: float) -> float:
+    return _load().oracle_trunc_kernel(float(t), float(sigma_r), int(N), float(eps))
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def bilateral(f, radius: int, sigma_r: float, N: int, eps: float = 0.0, truncated: bool = False,
+              return_pq: bool = False):
+    """Whole-image filter.  float32 input is widened exactly; float64 input is used as is."""
+    f = np.ascontiguousarray(f)
+    H, W = f.shape
+    out = np.empty((H, W), np.float64)
+    P = np.empty((H, W), np.float64) if return_pq else None
+    Q = np.empty((H, W), np.float64) if return_pq else None
+    lib = _load()
+    if f.dtype == np.float64:
+        lib.oracle_bilateral_f64(_ptr(f, _dp), H, W, int(radius), float(sigma_r), int(N), float(eps),
+                                 int(bool(truncated)), _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    else:
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        lib.oracle_bilateral(_ptr(f, _fp), H, W, int(radius), float(sigma_r), int(N), float(eps),
+                             int(bool(truncated)), _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    return (out, P, Q) if return_pq else out
+
+
+def bilateral_at(f, idx, radius: int, sigma_r: float, N: int, eps: float = 0.0, truncated: bool = False,
+                 return_pq: bool = False):
+    """Filter output at the flat (row-major) pixel indices ``idx`` only."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    H, W = f.shape
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = idx.size
+    out = np.empty(n, np.float64)
+    P = np.empty(n, np.float64) if return_pq else None
+    Q = np.empty(n, np.float64) if return_pq else None
+    _load().oracle_bilateral_at(_ptr(f, _fp), H, W, int(radius), float(sigma_r), int(N), float(eps),
+                                int(bool(truncated)), _ptr(idx, _llp), n, _ptr(out, _dp), _ptr(P, _dp),
+                                _ptr(Q, _dp))
+    return (out, P, Q) if return_pq else out
+
+
+def bilateral_grad(f, gbar, radius: int, sigma_r: float, N: int):
+    """(dL/df, dL/dsigma_r, out) for upstream gradient gbar = dL/d out; FP64 throughout."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    gbar = np.ascontiguousarray(gbar, dtype=np.float64)
+    H, W = f.shape
+    gf = np.empty((H, W), np.float64)
+    u = np.empty((H, W), np.float64)
+    gs = ctypes.c_double(0.0)
+    _load().oracle_bilateral_grad_f64(_ptr(f, _dp), _ptr(gbar, _dp), H, W, int(radius), float(sigma_r),
+                                      int(N), _ptr(gf, _dp), ctypes.byref(gs), _ptr(u, _dp))
+    return gf, gs.value, u

@@ -1,0 +1,346 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests re-evaluates the oracle's own formula: each compares the
+oracle with an independent route (exact binomial expansion, closed forms,
+integral-image box means, brute force with exact integer weights, a NumPy
+moving-sum evaluation of the expansion, finite differences) or checks an
+invariant of eq. (3).  The paper prints no worked numerical example.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1107_4617_amd import workloads as wl
+
+T = 255.0
+
+
+def _binom_kernel(t, sigma_r, N):
+    """phi(t) through the binomial expansion cos^N a = 2^-N sum_n C(N,n) cos((2n-N) a),
+    with exact integer binomials and exactly rounded weights (Section 1: a sum of
+    exponentials; Section 3: q_N has order N+1)."""
+    if N == 0:
+        return 1.0
+    a = t / (sigma_r * math.sqrt(N))
+    return math.fsum((math.comb(N, n) / 2 ** N) * math.cos((2 * n - N) * a) for n in range(N + 1))
+
+
+# ---------------------------------------------------------------- P1 ---------
+def test_shift_identity():
+    """cos(x - tau) = cos(tau) cos(x) + sin(tau) sin(x) (Section 1): the rule that
+    recombines per-order box sums into the kernel at f(x)."""
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-50, 50, 10000)
+    tau = rng.uniform(-50, 50, 10000)
+    lhs = np.cos(x - tau)
+    rhs = np.cos(tau) * np.cos(x) + np.sin(tau) * np.sin(x)
+    assert np.max(np.abs(lhs - rhs)) < 1e-13
+
+
+# ---------------------------------------------------------------- P2 ---------
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 30, 43, 117, 264])
+def test_kernel_matches_binomial_expansion(oracle, N):
+    """The oracle's cos^N (repeated squaring) equals the exact finite exponential sum."""
+    rng = np.random.default_rng(100 + N)
+    sigma = 30.0
+    s = sigma * math.sqrt(max(N, 1))
+    # |a| <= pi/2, plus a few arguments beyond it where cos < 0 (odd N keeps the sign)
+    ts = np.concatenate([rng.uniform(-math.pi / 2, math.pi / 2, 200) * s,
+                         rng.uniform(-3.0, 3.0, 50) * s])
+    err = max(abs(oracle.kernel(t, sigma, N) - _binom_kernel(t, sigma, N)) for t in ts)
+    assert err <= 1e-13, err
+
+
+def test_kernel_derivative_matches_difference_quotient(oracle):
+    for N in (1, 2, 30, 43):
+        for t in (-200.0, -31.0, 0.0, 7.5, 120.0):
+            h = 1e-4
+            fd = (_binom_kernel(t + h, 25.0, N) - _binom_kernel(t - h, 25.0, N)) / (2 * h)
+            assert abs(oracle.kernel_deriv(t, 25.0, N) - fd) < 1e-9
+
+
+# ---------------------------------------------------------------- P3 ---------
+def test_gaussian_convergence_rate(oracle):
+    """Theorem 3.3, eq. (6): cos^N(t/(sigma sqrt N)) -> exp(-t^2/(2 sigma^2)).
+    From log cos u = -u^2/2 - u^4/12 - ..., N * sup_t |phi_N - G| -> 16 e^-2 / 12 = 4/(3 e^2)."""
+    sigma = 30.0
+    t = np.linspace(0.0, 8 * sigma, 4001)
+    G = np.exp(-t ** 2 / (2 * sigma ** 2))
+    limit = 4.0 / (3.0 * math.e ** 2)
+    prev = None
+    for N in (10, 30, 100, 300, 1000, 3000):
+        phi = np.array([oracle.kernel(x, sigma, N) for x in t])
+        sup = np.max(np.abs(phi - G))
+        if prev is not None:
+            assert sup < prev  # monotone decrease
+        prev = sup
+        if N >= 300:
+            assert abs(N * sup - limit) / limit < 0.02, (N, N * sup)
+
+
+# ---------------------------------------------------------------- N_0 --------
+@pytest.mark.parametrize("sigma,expect", [(30.0, 30), (25.0, 43), (15.0, 118), (10.0, 264), (60.0, 8)])
+def test_order_threshold(oracle, sigma, expect):
+    """Section 3.1: N_0 = O(T^2/sigma^2) is the smallest order for which the kernel is
+    non-negative and unimodal on [-T, T]; with the eq. (6) scaling that is the smallest N
+    with T/(sigma sqrt N) <= pi/2."""
+    N0 = oracle.order_for(sigma, T)
+    assert N0 == expect
+    assert T / (sigma * math.sqrt(N0)) <= math.pi / 2
+    assert T / (sigma * math.sqrt(N0 - 1)) > math.pi / 2
+    # non-negative on [-T, T] at N_0 (even or odd N)
+    ts = np.linspace(-T, T, 2001)
+    assert min(oracle.kernel(t, sigma, N0) for t in ts) >= 0.0
+
+
+# ---------------------------------------------------------------- P4 ---------
+@pytest.mark.parametrize("r,N", [(0, 30), (2, 1), (3, 30), (5, 117), (40, 8)])
+def test_constant_image_is_fixed(oracle, r, N):
+    for c in (0.0, 17.25, 255.0):
+        f = np.full((9, 14), c, np.float32)
+        out = oracle.bilateral(f, r, 30.0, N)
+        assert np.max(np.abs(out - c)) <= 1e-14 * max(c, 1.0)
+
+
+# ---------------------------------------------------------------- P5 ---------
+def _box_mean(f, r):
+    """Truncated-window mean through an integral image (Section 2: Sum(F, x, T))."""
+    H, W = f.shape
+    S = np.zeros((H + 1, W + 1))
+    S[1:, 1:] = np.cumsum(np.cumsum(f.astype(np.float64), 0), 1)
+    i = np.arange(H)[:, None]
+    j = np.arange(W)[None, :]
+    y0, y1 = np.maximum(i - r, 0), np.minimum(i + r, H - 1) + 1
+    x0, x1 = np.maximum(j - r, 0), np.minimum(j + r, W - 1) + 1
+    tot = S[y1, x1] - S[y0, x1] - S[y1, x0] + S[y0, x0]
+    cnt = (y1 - y0) * (x1 - x0)
+    return tot / cnt
+
+
+def test_radius_zero_is_identity(oracle):
+    f = wl.random_image(11, 13, 3)
+    out = oracle.bilateral(f, 0, 30.0, 30)
+    assert np.array_equal(out, f.astype(np.float64))
+
+
+@pytest.mark.parametrize("r", [1, 3, 8, 30])
+def test_order_zero_is_box_mean(oracle, r):
+    """N = 0 (allowed in Section 3) makes the range kernel constant: eq. (3) becomes the
+    normalised moving sum of eq. (2) with a box."""
+    f = wl.random_image(15, 21, 4)
+    out = oracle.bilateral(f, r, 30.0, 0)
+    assert np.max(np.abs(out - _box_mean(f, r))) < 1e-11
+
+
+def test_wide_range_kernel_is_box_mean(oracle):
+    f = wl.random_image(12, 10, 5)
+    out = oracle.bilateral(f, 3, 1e9, 30)
+    assert np.max(np.abs(out - _box_mean(f, 3))) < 1e-9
+
+
+# ---------------------------------------------------------------- P6 ---------
+def test_shift_scale_and_symmetry_covariance(oracle):
+    rng = np.random.default_rng(6)
+    f = rng.uniform(0, 200, (13, 17))
+    base = oracle.bilateral(f, 3, 25.0, 43)
+    # shift: phi depends on differences only
+    assert np.max(np.abs(oracle.bilateral(f + 40.0, 3, 25.0, 43) - (base + 40.0))) < 1e-10
+    # scale: phi(a t; a sigma) = phi(t; sigma); a = 2 is exact in binary
+    assert np.max(np.abs(oracle.bilateral(2.0 * f, 3, 50.0, 43) - 2.0 * base)) < 1e-11
+    # transpose and flips: the square window is symmetric
+    assert np.max(np.abs(oracle.bilateral(np.ascontiguousarray(f.T), 3, 25.0, 43) - base.T)) < 1e-11
+    assert np.max(np.abs(oracle.bilateral(np.ascontiguousarray(f[::-1]), 3, 25.0, 43) - base[::-1])) < 1e-11
+    assert np.max(np.abs(oracle.bilateral(np.ascontiguousarray(f[:, ::-1]), 3, 25.0, 43) - base[:, ::-1])) < 1e-11
+
+
+# ---------------------------------------------------------------- P7 ---------
+def test_two_level_closed_form(oracle):
+    """Levels a (left block of columns) and b (right): at a pixel of level a whose window
+    holds n_a pixels of a and n_b of b, eq. (3) gives
+    (n_a a + n_b b phi(b-a)) / (n_a + n_b phi(b-a)), with n_a, n_b counted by hand."""
+    H, W, split, r = 10, 12, 5, 2
+    a, b = 60.0, 100.0
+    sigma, N = 30.0, 30
+    f = np.full((H, W), a)
+    f[:, split:] = b
+    out = oracle.bilateral(f, r, sigma, N)
+    phi_ab = _binom_kernel(b - a, sigma, N)
+    for i in range(H):
+        for j in range(W):
+            rows = min(H - 1, i + r) - max(0, i - r) + 1
+            c0, c1 = max(0, j - r), min(W - 1, j + r)
+            na = rows * max(0, min(c1, split - 1) - c0 + 1)
+            nb = rows * max(0, c1 - max(c0, split) + 1)
+            if f[i, j] == a:
+                expect = (na * a + nb * b * phi_ab) / (na + nb * phi_ab)
+            else:
+                expect = (nb * b + na * a * phi_ab) / (nb + na * phi_ab)
+            assert abs(out[i, j] - expect) < 1e-12
+
+
+# ---------------------------------------------------------------- P8 ---------
+def test_convex_combination_bounds(oracle):
+    """With N >= N_0 and data in [0, T] the kernel is non-negative (Section 3), so each output
+    is a convex combination of its window."""
+    f = wl.random_image(20, 23, 8)
+    N0 = oracle.order_for(20.0, T)
+    out = oracle.bilateral(f, 4, 20.0, N0)
+    from numpy.lib.stride_tricks import sliding_window_view
+    pad_lo = np.pad(f.astype(np.float64), 4, constant_values=np.inf)
+    pad_hi = np.pad(f.astype(np.float64), 4, constant_values=-np.inf)
+    mn = sliding_window_view(pad_lo, (9, 9)).min(axis=(-1, -2))
+    mx = sliding_window_view(pad_hi, (9, 9)).max(axis=(-1, -2))
+    assert np.all(out >= mn - 1e-12) and np.all(out <= mx + 1e-12)
+
+
+# ---------------------------------------------------------------- P9 ---------
+def _brute(f, r, sigma, N):
+    """Pure-Python eq. (3) with the kernel taken as the exact binomial sum of exponentials."""
+    H, W = f.shape
+    P = np.empty((H, W))
+    Q = np.empty((H, W))
+    if N == 0:
+        w = [1.0]
+        om = [0.0]
+    else:
+        s = sigma * math.sqrt(N)
+        w = [math.comb(N, n) / 2 ** N for n in range(N + 1)]
+        om = [(2 * n - N) / s for n in range(N + 1)]
+    for i in range(H):
+        for j in range(W):
+            fx = float(f[i, j])
+            ps, qs = [], []
+            for y in range(max(0, i - r), min(H - 1, i + r) + 1):
+                for x in range(max(0, j - r), min(W - 1, j + r) + 1):
+                    fy = float(f[y, x])
+                    k = math.fsum(wn * math.cos(o * (fy - fx)) for wn, o in zip(w, om))
+                    ps.append(k * fy)
+                    qs.append(k)
+            P[i, j] = math.fsum(ps)
+            Q[i, j] = math.fsum(qs)
+    return P, Q
+
+
+@pytest.mark.parametrize("r,N,shape", [(0, 2, (7, 5)), (1, 1, (13, 17)), (3, 30, (16, 16)),
+                                       (7, 2, (11, 16)), (20, 30, (9, 13)), (2, 117, (6, 9))])
+def test_brute_force_small(oracle, r, N, shape):
+    """P and Q are compared (below N_0 the kernel changes sign and the ratio can be
+    ill-conditioned); the ratio is compared where Q is bounded away from zero."""
+    f = wl.random_image(*shape, seed=9 + r)
+    Pr, Qr = _brute(f, r, 30.0, N)
+    out, P, Q = oracle.bilateral(f, r, 30.0, N, return_pq=True)
+    nwin = (2 * r + 1) ** 2
+    assert np.max(np.abs(P - Pr)) <= 1e-13 * nwin * T
+    assert np.max(np.abs(Q - Qr)) <= 1e-13 * nwin
+    ok = np.abs(Qr) > 0.5
+    assert np.max(np.abs(out - Pr / Qr)[ok]) <= 1e-12 * T
+
+
+# ---------------------------------------------------------------- P10 --------
+def _folded_shiftable(f, r, sigma, N):
+    """Algorithm 2 with one spatial basis function (the box), in NumPy FP64: fold terms n and
+    N-n, form cos/sin channels and their f-weighted copies, box-sum each through an
+    integral image, recombine with the shift identity, take the ratio."""
+    f = f.astype(np.float64)
+    H, W = f.shape
+
+    def box(X):
+        S = np.zeros((H + 1, W + 1))
+        S[1:, 1:] = np.cumsum(np.cumsum(X, 0), 1)
+        i = np.arange(H)[:, None]
+        j = np.arange(W)[None, :]
+        y0, y1 = np.maximum(i - r, 0), np.minimum(i + r, H - 1) + 1
+        x0, x1 = np.maximum(j - r, 0), np.minimum(j + r, W - 1) + 1
+        return S[y1, x1] - S[y0, x1] - S[y1, x0] + S[y0, x0]
+
+    P = np.zeros((H, W))
+    Q = np.zeros((H, W))
+    s = sigma * math.sqrt(N)
+    for n in range((N + 1) // 2):
+        v = 2.0 * math.comb(N, n) / 2 ** N
+        om = (N - 2 * n) / s
+        C, S_ = np.cos(om * f), np.sin(om * f)
+        P += v * (C * box(f * C) + S_ * box(f * S_))
+        Q += v * (C * box(C) + S_ * box(S_))
+    if N % 2 == 0:
+        v = math.comb(N, N // 2) / 2 ** N
+        P += v * box(f)
+        Q += v * box(np.ones_like(f))
+    return P / Q
+
+
+@pytest.mark.parametrize("r,N", [(2, 30), (5, 43), (4, 117), (6, 7)])
+def test_folded_moving_sum_evaluation(oracle, r, N):
+    f = wl.smooth_image(40, 56, seed=1)
+    ref = _folded_shiftable(f, r, 30.0, N)
+    out = oracle.bilateral(f, r, 30.0, N)
+    assert np.max(np.abs(out - ref)) <= 1e-11 * T
+
+
+# ---------------------------------------------------------------- P11 --------
+@pytest.mark.parametrize("shape,r,sigma,N", [((9, 11), 2, 30.0, 30), ((8, 10), 3, 25.0, 43), ((7, 6), 1, 40.0, 5)])
+def test_gradient_matches_central_differences(oracle, shape, r, sigma, N):
+    rng = np.random.default_rng(12)
+    f = rng.uniform(20, 230, shape)
+    g = rng.normal(size=shape)
+    gf, gs, u = oracle.bilateral_grad(f, g, r, sigma, N)
+    assert np.max(np.abs(u - oracle.bilateral(f, r, sigma, N))) < 1e-12
+
+    def L(ff, ss):
+        return float(np.sum(g * oracle.bilateral(ff, r, ss, N)))
+
+    h = 1e-3
+    fd = np.empty(shape)
+    for i in range(shape[0]):
+        for j in range(shape[1]):
+            fp = f.copy(); fp[i, j] += h
+            fm = f.copy(); fm[i, j] -= h
+            fd[i, j] = (L(fp, sigma) - L(fm, sigma)) / (2 * h)
+    assert np.max(np.abs(gf - fd)) <= 1e-6 * np.max(np.abs(fd))
+    fds = (L(f, sigma + h) - L(f, sigma - h)) / (2 * h)
+    assert abs(gs - fds) <= 1e-6 * abs(fds)
+
+
+# ---------------------------------------------------------------- P12 --------
+@pytest.mark.parametrize("N,eps", [(30, 1e-7), (117, 1e-7), (264, 1e-7), (43, 1e-4)])
+def test_truncation_bound_and_counts(oracle, N, eps):
+    """Discarding basis functions with w_n < eps (Section 3.1) changes the kernel by at most
+    the dropped weight mass, everywhere."""
+    kept, dropped = oracle.trunc_terms(N, eps)
+    exact_w = [math.comb(N, n) / 2 ** N for n in range(N + 1)]
+    assert kept == sum(1 for w in exact_w if w >= eps)
+    assert abs(dropped - math.fsum(w for w in exact_w if w < eps)) <= 1e-12 * max(dropped, 1e-300)
+    sigma = 15.0
+    ts = np.linspace(-T, T, 1001)
+    dev = max(abs(oracle.kernel(t, sigma, N) - oracle.trunc_kernel(t, sigma, N, eps)) for t in ts)
+    # plus the rounding of log-gamma weights, |lgamma(N+1)| * 2^-52 ~ 3e-13 at N = 264
+    assert dev <= dropped + 1e-12
+
+
+def test_truncated_filter_reduces_to_exact_when_nothing_dropped(oracle):
+    f = wl.random_image(10, 12, 13)
+    a = oracle.bilateral(f, 2, 30.0, 30)
+    b = oracle.bilateral(f, 2, 30.0, 30, eps=0.0, truncated=True)
+    assert np.max(np.abs(a - b)) < 1e-11
+
+
+def test_sampled_matches_full(oracle):
+    f = wl.rect_image(40, 50, seed=2)
+    full, P, Q = oracle.bilateral(f, 6, 30.0, 30, return_pq=True)
+    idx = np.array([0, 7, 49, 50, 1999, 1234, 999])
+    o, p, q = oracle.bilateral_at(f, idx, 6, 30.0, 30, return_pq=True)
+    assert np.array_equal(o, full.ravel()[idx])
+    assert np.array_equal(p, P.ravel()[idx]) and np.array_equal(q, Q.ravel()[idx])
+
+
+def test_huge_radius_covers_whole_image(oracle):
+    f = wl.random_image(6, 9, 14)
+    a = oracle.bilateral(f, 9, 30.0, 30)
+    b = oracle.bilateral(f, 2 ** 30, 30.0, 30)
+    assert np.array_equal(a, b)
+    # every pixel sees every pixel: compare with direct whole-image sums
+    ff = f.astype(np.float64).ravel()
+    for x in (0, 17, 53):
+        k = np.array([_binom_kernel(fy - ff[x], 30.0, 30) for fy in ff])
+        assert abs(a.ravel()[x] - (k * ff).sum() / k.sum()) < 1e-10
