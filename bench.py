@@ -1,0 +1,207 @@
+"""Benchmark of the constant-time bilateral filter on one MI355X.
+
+One step = one plain FP32 forward pass of the whole filter (plan, pointwise
+transforms, horizontal and vertical moving sums, recombination, ratio) over a
+4096x4096 synthetic "rect" image (64 random rectangles + N(0, 20^2) noise),
+box radius 20, sigma_r = 30, T = 255, N = 30 (16 folded orders).  Inputs are
+resident in HBM before timing starts; steps are timed with HIP events on the
+stream the library launches on.  The same run also times, at their own
+workloads, the training forward + adjoint, the BF16 precision form and the
+batched persistent/graph launch, and the FP64 CPU oracle on a bounded sample
+of the headline workload (reported as cpu_baseline).
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
+# Algorithmic FP32 work of the method per (pixel, folded order): rotation of
+# (cos, sin) 6, f-weighted channels 2, four channels x two directions x two
+# running-sum updates 16, recombination of P and Q 10.
+FLOP_PER_PX_ORDER = 34
+BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_calls(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        fn()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return float(np.mean(ms)), float(np.median(ms)), wall
+
+
+def cpu_baseline(img, radius, sigma, N, budget_s=12.0):
+    import oracle
+    H, W = img.shape
+    rng = np.random.default_rng(123)
+    n0 = 2000
+    idx = rng.integers(0, H * W, n0)
+    t0 = time.perf_counter()
+    oracle.bilateral_at(img, idx, radius, sigma, N)
+    t_cal = time.perf_counter() - t0
+    n = int(min(H * W, max(n0, n0 * budget_s / max(t_cal, 1e-6))))
+    idx = rng.integers(0, H * W, n)
+    t0 = time.perf_counter()
+    oracle.bilateral_at(img, idx, radius, sigma, N)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt / 1e6, "unit": "Mpixel/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} seeded random pixels of the {H}x{W} r={radius} image, direct FP64 window sums "
+                      f"({(2 * radius + 1) ** 2} kernel evaluations per pixel), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1107_4617_amd import (bilateral, bilateral_backward, bilateral_batched, bilateral_train,
+                                     plan_info)
+    from paper_1107_4617_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    H = W = 4096
+    radius, sigma, T, N = 20, 30.0, 255.0, 30
+    K, _ = plan_info(N, 0.0)
+    log("generating rect4096 image")
+    img_np = wl.rect_image(H, W, seed=2)
+    img = torch.from_numpy(img_np).to(dev)
+    out = torch.empty_like(img)
+
+    fwd = lambda: bilateral(img, radius, sigma, T, N=N, out=out)  # noqa: E731
+    log("timing FP32 forward")
+    mean_ms, med_ms, wall = time_calls(fwd, args.steps, args.warmup, stream)
+    px = H * W
+    value = px / (mean_ms * 1e-3) / 1e6
+    flops = FLOP_PER_PX_ORDER * K * px
+    achieved = flops / (mean_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "Mpixel/s + %HBM roofline, 4096^2 r=20 sigma_r=30 (plain FP32 forward)",
+        "value": round(value, 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mean_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rect4096_r20_s30", "H": H, "W": W, "radius": radius, "sigma_r": sigma, "T": T,
+                   "N": N, "folded_orders": K},
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None,
+            "kernel": "strip_kernel<float,256,16,PolForward>",
+            "flop_per_launch": flops,
+            "hbm_frac": round(BYTES_PER_PX * px / (mean_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        },
+        "median_ms": round(med_ms, 4),
+    }
+
+    if not args.no_extra:
+        variants = {}
+        # BF16 precision form at the headline workload (weights below 1e-7 dropped)
+        kb, eps = plan_info(N, 1e-7)
+        outb = torch.empty_like(img)
+        log("timing BF16 precision form")
+        ms_b, _, _ = time_calls(lambda: bilateral(img, radius, sigma, T, N=N, precision="bf16", weight_eps=1e-7,
+                                                  kahan=True, out=outb), args.steps, args.warmup, stream)
+        variants["bf16_kahan_trunc1e-7"] = {"Mpixel/s": round(px / ms_b / 1e3, 2), "ms": round(ms_b, 4),
+                                            "folded_orders": kb, "dropped_weight": eps,
+                                            "max_abs_vs_fp32": float((outb - out).abs().max())}
+        # training forward + adjoint at the headline workload
+        g = torch.randn_like(img)
+        holder = {}
+
+        def fb():
+            o, s = bilateral_train(img, radius, sigma, T, N)
+            bilateral_backward(img, g, radius, sigma, T, N, out=o, saved=s)
+
+        log("timing forward+backward")
+        ms_fb, _, _ = time_calls(fb, max(3, args.steps // 2), 1, stream)
+        variants["fwd_bwd_fp32"] = {"Mpixel/s": round(px / ms_fb / 1e3, 2), "ms": round(ms_fb, 4)}
+        del g, holder
+        # differentiation workload: 16 x 1024^2, r=10, sigma_r=25, N=43
+        log("timing 16x1024^2 fwd+bwd")
+        pairs = [wl.denoise_pair(i) for i in range(16)]
+        xs = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+        ts = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+
+        def fb16():
+            for x, t in zip(xs, ts):
+                o, s = bilateral_train(x, 10, 25.0, T, 43)
+                gg = (2.0 / x.numel()) * (o - t)
+                bilateral_backward(x, gg, 10, 25.0, T, 43, out=o, saved=s)
+
+        ms16, _, _ = time_calls(fb16, 3, 1, stream)
+        variants["denoise16x1024_fwd_bwd"] = {"Mpixel/s": round(16 * 1024 * 1024 / ms16 / 1e3, 2),
+                                              "ms": round(ms16, 3)}
+        del xs, ts, pairs
+        # batched workload: 256 images, graph replay
+        log("generating 256-image batch")
+        specs = wl.batch_specs(256, seed=4)
+        imgs = [torch.from_numpy(wl.gradient_image(h, w, s)).to(dev) for (h, w, r, sg, s) in specs]
+        outs = [torch.empty_like(x) for x in imgs]
+        radii, sigs = [s[2] for s in specs], [s[3] for s in specs]
+        tot_px = sum(h * w for (h, w, *_r) in specs)
+        side = torch.cuda.Stream()
+        log("timing batched graph")
+        with torch.cuda.stream(side):
+            ms_bt, _, _ = time_calls(lambda: bilateral_batched(imgs, radii, sigs, T, outs=outs, graph_key=4),
+                                     5, 1, side)
+        variants["batched256_graph"] = {"Mpixel/s": round(tot_px / ms_bt / 1e3, 2), "ms": round(ms_bt, 3),
+                                        "pixels": tot_px}
+        del imgs, outs
+        rec["variants"] = variants
+
+    if not args.no_cpu:
+        log("timing CPU oracle sample")
+        rec["cpu_baseline"] = cpu_baseline(img_np, radius, sigma, N)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

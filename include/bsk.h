@@ -1,0 +1,206 @@
+/*
+ * bsk.h — C ABI of libbsk: constant-time bilateral filtering with shiftable
+ * kernels on AMD Instinct MI355X (gfx950).
+ *
+ * Method (K. N. Chaudhury, "Constant-time filtering using shiftable kernels"):
+ * eq. (3) of Section 2 defines the bilateral filter
+ *     out(x) = sum_{y in B(x)} phi(f(y) - f(x)) f(y)  /  sum_{y in B(x)} phi(f(y) - f(x)).
+ * Here the spatial kernel is a box: B(x) is the (2r+1)x(2r+1) square centred
+ * at x, truncated at the image border (pixels outside the image are absent).
+ * The range kernel is the raised cosine q_N of Section 3 in the scaling of
+ * Theorem 3.3, eq. (6): phi(t) = cos^N(t / (sigma_r sqrt N)), which tends to
+ * the Gaussian exp(-t^2 / 2 sigma_r^2).  Being a finite sum of N+1 complex
+ * exponentials (Section 1), phi is shiftable, so Algorithm 2 computes the
+ * filter exactly (up to rounding) from O(1)-per-pixel moving sums
+ * (Section 2, Sum(F, x, T)) of pointwise transforms of f.
+ *
+ * T is the range bound of Section 3 (values are assumed to span at most T).
+ * It only selects the automatic order N_0 = ceil((2T / (pi sigma_r))^2), the
+ * smallest order for which phi is non-negative and unimodal on [-T, T]
+ * (Section 3.1: N_0 = O(T^2 / sigma^2)).
+ *
+ * Conventions for every entry point:
+ *   - Image pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors),
+ *     row-major, H rows of W elements, element pitch = W unless a pitch is
+ *     given in bsk_options.  The caller owns every buffer.
+ *   - The library never allocates the caller's outputs.  It may allocate a
+ *     device workspace (cached per device, released by bsk_release()).
+ *   - Every call that takes a `stream` (a hipStream_t; NULL = the default
+ *     stream) is asynchronous on that stream.  bilateral_shiftable() uses the
+ *     default stream and returns after its work completes.
+ *   - Errors are returned as bsk_status codes, never thrown; bsk_last_error()
+ *     returns a thread-local message for the last failing call.  Arguments are
+ *     validated before any work is queued: on an error nothing is launched.
+ *     Faults inside a kernel surface at the next synchronising call.
+ *   - Preconditions that are not checked: inputs are finite (a NaN spreads
+ *     along the running sums of its row strip); input and output buffers do
+ *     not overlap except where an argument says so.
+ *   - radius may exceed the image: the window is clamped to the image, so
+ *     radius >= max(H, W) - 1 gives the whole-image filter.  Radii whose
+ *     clamped value exceeds BSK_MAX_RADIUS are rejected with BSK_EUNSUPPORTED.
+ */
+#ifndef BSK_H
+#define BSK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSK_OK = 0,
+    BSK_EINVAL = -1,        /* bad argument (null pointer, size, non-finite sigma_r/T, ...) */
+    BSK_ERANGE = -2,        /* order too large (more than BSK_MAX_ORDERS folded orders) */
+    BSK_ENOMEM = -3,        /* workspace allocation failed */
+    BSK_EHIP = -4,          /* HIP runtime error (no device, launch failure, ...) */
+    BSK_EUNSUPPORTED = -5   /* valid request this build does not handle */
+} bsk_status;
+
+typedef enum {
+    BSK_FP32 = 0,   /* FP32 data, FP32 transforms, sums and recombination */
+    BSK_BF16 = 1,   /* precision form: stack quantised to bfloat16, FP32 sums */
+    BSK_FP16 = 2,   /* precision form: stack quantised to float16, FP32 sums */
+    BSK_FP64 = 3,   /* FP64 data and arithmetic end to end (img/out are double*) */
+    BSK_I16 = 4     /* precision form: stack quantised to 16-bit fixed point (Q15), FP32 sums */
+} bsk_precision;
+
+#define BSK_MAX_ORDERS 256     /* folded orders after truncation: N <= 511 untruncated */
+#define BSK_MAX_RADIUS 500     /* clamped radius limit of the fused kernels */
+
+/* Options; a zero-initialised struct means: automatic N_0, FP32, no
+ * truncation, no compensation, dense pitch, tuned launch shape. */
+typedef struct {
+    int order_mode;       /* 0: N = N_0 from sigma_r and T; 1: use `N` below */
+    int N;                /* range-kernel order when order_mode == 1 (N = 0 is the box mean) */
+    int precision;        /* bsk_precision */
+    double weight_eps;    /* drop binomial weights 2^-N C(N,n) < weight_eps (Section 3.1); 0 keeps all */
+    int kahan;            /* 1: Kahan-compensated FP32 vertical running sums */
+    int pitch_in;         /* input row pitch in elements; 0 = W */
+    int pitch_out;        /* output row pitch in elements; 0 = W */
+    int block;            /* lanes per workgroup (256, 512, 1024); 0 = auto */
+    int strip_h;          /* output rows per workgroup; 0 = auto */
+} bsk_options;
+
+/*
+ * Bilateral filter of one FP32 image (eq. (3), Algorithm 2 with a box spatial
+ * kernel and the raised-cosine range kernel at order N_0(sigma_r, T)).
+ *   img:    device, H*W floats, row-major (read only)
+ *   out:    device, H*W floats (written); must not overlap img
+ *   radius: box half-width r >= 0 (window (2r+1)^2)
+ *   sigma_r > 0: range scale (the Gaussian limit's standard deviation)
+ *   T > 0:  range bound, selects N_0
+ * Runs on the default stream and synchronises before returning.
+ */
+int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_r, float T,
+                        float *out);
+
+/*
+ * As bilateral_shiftable, with options and a stream (asynchronous).
+ * img/out are float* for BSK_FP32/BF16/FP16/I16 and double* for BSK_FP64.
+ * opt may be NULL (defaults).  If opt->weight_eps > 0, folded orders whose
+ * unfolded weight is below it are dropped (Section 3.1); the dropped mass is
+ * reported by bsk_plan_info().
+ */
+int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigma_r, float T,
+                           void *out, const bsk_options *opt, void *stream);
+
+/*
+ * Training forward (FP32): the filter output plus what the adjoint needs.
+ *   out:   device H*W floats: u = P/Q
+ *   saved: device 3*H*W floats, planar: Q (the normaliser eta of eq. (3)),
+ *          E1(z) = sum_{y in B(z)} phi'(f_y - f_z)(f_y - u_z),
+ *          E2(x) = sum_{y in B(x)} (f_y - f_x) phi'(f_y - f_x)(f_y - u_x).
+ * opt may be NULL; only FP32 is supported (BSK_EUNSUPPORTED otherwise).
+ */
+int bilateral_shiftable_train(const float *img, int H, int W, int radius, float sigma_r, float T,
+                              const bsk_options *opt, float *out, float *saved, void *stream);
+
+/*
+ * Adjoint of the filter (FP32), by differentiating eq. (3) through the
+ * shiftable expansion: the adjoint of a box moving sum is a box moving sum,
+ * so d/df is again one pass of Algorithm 2 over the channels
+ * (a cos, a sin, a u cos, a u sin), a = grad_out / Q.  N is held fixed.
+ *   img:       device H*W input image
+ *   grad_out:  device H*W, dL/d out
+ *   out,saved: from bilateral_shiftable_train on the same img and parameters;
+ *              both NULL makes the call recompute them into the workspace
+ *   grad_img:  device H*W (written), or NULL to skip
+ *   grad_sigma: device pointer to ONE float (written: dL/d sigma_r), or NULL.
+ *              The reduction is deterministic (fixed order, no atomics).
+ */
+int bilateral_shiftable_backward(const float *img, const float *grad_out, const float *out,
+                                 const float *saved, int H, int W, int radius, float sigma_r,
+                                 float T, const bsk_options *opt, float *grad_img,
+                                 float *grad_sigma, void *stream);
+
+/* One image of a batched call (FP32, device pointers, dense pitch). */
+typedef struct {
+    const float *img;
+    float *out;
+    int H, W;
+    int radius;
+    float sigma_r;
+    int N;            /* < 0: N_0(sigma_r, T); >= 0: explicit order */
+} bsk_image_desc;
+
+/*
+ * Filter B independent images of different sizes, radii and sigma_r in ONE
+ * persistent kernel launch.  descs is a HOST array of B descriptors.  Work
+ * units (image, strip, row segment) are claimed from a device work counter;
+ * the launch shape comes from the autotuner (bsk_autotune) when tuned.
+ * The descriptor table is staged through a library-owned device buffer, so
+ * consecutive batched calls on one device must be ordered on one stream.
+ */
+int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T,
+                                const bsk_options *opt, void *stream);
+
+/*
+ * Batched call recorded once into a HIP graph and replayed: the first call
+ * with a given `key` captures the launch (descriptor upload + kernel) on
+ * `stream`; later calls with the same key and the same descriptors replay it.
+ * Returns BSK_EINVAL if the descriptors differ from the captured ones.
+ */
+int bilateral_shiftable_batched_graph(const bsk_image_desc *descs, int B, float T,
+                                      const bsk_options *opt, int key, void *stream);
+
+/* N_0 = ceil((2T / (pi sigma_r))^2) (Section 3.1); -1 on invalid input. */
+int bsk_order_for(float sigma_r, float T);
+
+/* Folded plan of order N with truncation eps: number of folded orders K and
+ * the dropped unfolded weight mass (both may be NULL). */
+int bsk_plan_info(int N, double eps, int *K, double *dropped);
+
+/* Dropped unfolded weight mass sum_{w_n < eps} w_n (0 if nothing dropped). */
+double bsk_truncation_error(int N, double eps);
+
+/*
+ * Launch-shape autotuner.  Times the candidate shapes (lanes per workgroup in
+ * {256, 512, 1024} that fit the radius, output rows per workgroup in
+ * {16 .. 256}) of the single-image forward for this exact request on the
+ * current device, using the caller's img and out buffers (out is overwritten
+ * several times; the stream is synchronised), and caches the fastest.  Later
+ * calls with the same clamped radius, folded-order count, H, W and precision,
+ * and with opt->block == 0 and opt->strip_h == 0, use it.  `path` (nullable)
+ * names a JSON-lines cache file that is read first and rewritten with the
+ * result; the environment variable BSK_TUNE_CACHE names a file read at first
+ * use.  best_block, best_rows and best_ms (nullable) receive the winner.
+ */
+int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
+                 const bsk_options *opt, const char *path, void *stream, int *best_block,
+                 int *best_rows, double *best_ms);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *bsk_last_error(void);
+
+/* Frees every library-owned device buffer and graph. */
+int bsk_release(void);
+
+/* Library version string. */
+const char *bsk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSK_H */

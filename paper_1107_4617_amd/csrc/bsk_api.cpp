@@ -1,0 +1,404 @@
+// C ABI of libbsk: argument validation, planning, workspace and launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "bsk_host.h"
+
+namespace bsk {
+namespace host {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(BSK_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ----------------------------------------------------------- workspace --
+// One grow-only device buffer per (device, stream, slot).  Calls that share a
+// stream are ordered by it, so they may share the buffer.
+struct WsKey {
+    int dev;
+    void *stream;
+    int slot;
+    bool operator<(const WsKey &o) const
+    {
+        if (dev != o.dev) return dev < o.dev;
+        if (stream != o.stream) return stream < o.stream;
+        return slot < o.slot;
+    }
+};
+struct WsBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<WsKey, WsBuf> g_ws;
+
+int get_ws(void *stream, int slot, size_t bytes, void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsBuf &b = g_ws[WsKey{dev, stream, slot}];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            // the previous buffer may still be read by queued work on this stream
+            e = hipStreamSynchronize((hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            hipFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        e = hipMalloc(&b.ptr, bytes);
+        if (e != hipSuccess) {
+            b.ptr = nullptr;
+            (void)hipGetLastError();
+            return fail(BSK_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+        }
+        b.bytes = bytes;
+    }
+    *out = b.ptr;
+    return BSK_OK;
+}
+
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+// ----------------------------------------------------------- validation --
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r)
+{
+    if (H < 1 || W < 1) return fail(BSK_EINVAL, "image size %dx%d must be positive", H, W);
+    if (radius < 0) return fail(BSK_EINVAL, "radius %d must be >= 0", radius);
+    if (!finite_pos(sigma_r)) return fail(BSK_EINVAL, "sigma_r must be finite and > 0");
+    if (!finite_pos(T)) return fail(BSK_EINVAL, "T must be finite and > 0");
+    bsk_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    if (o.order_mode != 0 && o.order_mode != 1) return fail(BSK_EINVAL, "order_mode must be 0 or 1");
+    if (o.order_mode == 1 && o.N < 0) return fail(BSK_EINVAL, "N must be >= 0");
+    if (o.precision < BSK_FP32 || o.precision > BSK_I16) return fail(BSK_EINVAL, "unknown precision");
+    if (!(o.weight_eps >= 0.0) || !std::isfinite(o.weight_eps))
+        return fail(BSK_EINVAL, "weight_eps must be finite and >= 0");
+    if (o.pitch_in < 0 || o.pitch_out < 0) return fail(BSK_EINVAL, "pitches must be >= 0");
+    r->pitch_in = o.pitch_in ? o.pitch_in : W;
+    r->pitch_out = o.pitch_out ? o.pitch_out : W;
+    if (r->pitch_in < W || r->pitch_out < W) return fail(BSK_EINVAL, "pitch smaller than W");
+    r->prec = o.precision;
+    r->kahan = o.kahan ? 1 : 0;
+    const long long nmax = (long long)H * (long long)W;
+    if (nmax > (1LL << 40)) return fail(BSK_EINVAL, "image too large");
+
+    if (o.order_mode == 1) {
+        r->N = o.N;
+    } else {
+        const double x = 2.0 * (double)T / (M_PI * (double)sigma_r);
+        if (!(x * x < 1e7)) return fail(BSK_ERANGE, "automatic order N_0 too large");
+        r->N = bsk::order_for(sigma_r, T);
+    }
+    if (r->N > 1000000) return fail(BSK_ERANGE, "order N=%d too large", r->N);
+    if (bsk::make_plan(r->N, sigma_r, o.weight_eps, &r->plan) != 0)
+        return fail(BSK_ERANGE, "order N=%d leaves more than %d folded orders (raise weight_eps)", r->N,
+                    bsk::kMaxOrders);
+
+    // Clamping the radius to the image leaves every truncated window unchanged.
+    r->rh = radius < W - 1 ? radius : W - 1;
+    r->rv = radius < H - 1 ? radius : H - 1;
+    if (r->rh > BSK_MAX_RADIUS)
+        return fail(BSK_EUNSUPPORTED, "clamped radius %d exceeds %d", r->rh, BSK_MAX_RADIUS);
+
+    int block = o.block;
+    int tuned_S = 0;
+    if (o.block == 0 && o.strip_h == 0) {
+        int tb = 0, ts = 0;
+        if (tuned_shape(r->rh, r->plan.K, H, W, r->prec, &tb, &ts)) {
+            block = tb;
+            tuned_S = ts;
+        }
+    }
+    if (block == 0) {
+        block = 1024;
+        const int cands[3] = {256, 512, 1024};
+        for (int b : cands) {
+            if (b - 2 * r->rh >= b / 2) {
+                block = b;
+                break;
+            }
+        }
+    }
+    if (block != 256 && block != 512 && block != 1024)
+        return fail(BSK_EINVAL, "block must be 256, 512 or 1024");
+    if (block - 2 * r->rh < 1)
+        return fail(BSK_EUNSUPPORTED, "radius %d too large for a %d-lane strip", r->rh, block);
+    r->block = block;
+    if (o.strip_h < 0) return fail(BSK_EINVAL, "strip_h must be >= 0");
+    const int Wt = block - 2 * r->rh;
+    const int strips = (W + Wt - 1) / Wt;
+    if (o.strip_h > 0) {
+        r->S = o.strip_h;
+    } else if (tuned_S > 0) {
+        r->S = tuned_S;
+    } else {
+        // about four workgroups per compute unit (one resident at a time)
+        const int target = 4 * device_cus();
+        int segs = (target + strips - 1) / strips;
+        if (segs < 1) segs = 1;
+        int S = (H + segs - 1) / segs;
+        if (S < 16) S = 16;
+        r->S = S;
+    }
+    if (r->S > H) r->S = H;
+    return BSK_OK;
+}
+
+void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W)
+{
+    std::memset(a, 0, sizeof(*a));
+    a->io.H = H;
+    a->io.W = W;
+    a->io.pitch_in = r.pitch_in;
+    a->io.pitch_out = r.pitch_out;
+    a->rh = r.rh;
+    a->rv = r.rv;
+    a->S = r.S;
+    a->K = r.plan.K;
+    a->omega_base = r.plan.omega_base;
+    a->delta = r.plan.delta;
+    const int Wt = r.block - 2 * r.rh;
+    a->strips = (W + Wt - 1) / Wt;
+    for (int m = 0; m < r.plan.K; ++m) a->v[m] = r.plan.v[m];
+}
+
+int nblocks(const Resolved &r, int H, int W)
+{
+    const int Wt = r.block - 2 * r.rh;
+    return ((W + Wt - 1) / Wt) * ((H + r.S - 1) / r.S);
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace host
+}  // namespace bsk
+
+using namespace bsk::host;
+
+namespace {
+
+int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
+                 const bsk_options *opt, void *stream)
+{
+    if (!img || !out) return fail(BSK_EINVAL, "null image pointer");
+    Resolved r;
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r);
+    if (st) return st;
+    const size_t esz = r.prec == BSK_FP64 ? 8 : 4;
+    if (overlap(img, ((size_t)(H - 1) * r.pitch_in + W) * esz, out, ((size_t)(H - 1) * r.pitch_out + W) * esz))
+        return fail(BSK_EINVAL, "img and out overlap");
+    bsk::StripArgs a;
+    fill_args(&a, r, H, W);
+    a.io.img = img;
+    a.io.out = out;
+    const int kc = r.prec == BSK_FP64 ? bsk::chunk_forward_f64(r.block) : bsk::chunk_forward_f32(r.block);
+    if (r.plan.K > kc) {
+        void *ws = nullptr;
+        st = get_ws(stream, 0, (size_t)bsk::acc_count_forward() * H * W * esz, &ws);
+        if (st) return st;
+        a.ws = ws;
+    }
+    hipError_t e = r.prec == BSK_FP64
+                       ? bsk::launch_forward_f64(a, r.block, (hipStream_t)stream)
+                       : bsk::launch_forward_f32(a, r.block, r.prec, r.kahan, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return BSK_OK;
+}
+
+int train_impl(const float *img, int H, int W, const Resolved &r, float *out, float *saved, void *stream)
+{
+    bsk::StripArgs a;
+    fill_args(&a, r, H, W);
+    a.io.img = img;
+    a.io.out = out;
+    a.io.out2 = saved;
+    if (r.plan.K > bsk::chunk_train_f32(r.block)) {
+        void *ws = nullptr;
+        int st = get_ws(stream, 1, (size_t)bsk::acc_count_train() * H * W * 4, &ws);
+        if (st) return st;
+        a.ws = ws;
+    }
+    hipError_t e = bsk::launch_train_f32(a, r.block, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "train launch");
+    return BSK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_r, float T, float *out)
+{
+    int st = forward_impl(img, H, W, radius, sigma_r, T, out, nullptr, nullptr);
+    if (st) return st;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return BSK_OK;
+}
+
+int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
+                           const bsk_options *opt, void *stream)
+{
+    return forward_impl(img, H, W, radius, sigma_r, T, out, opt, stream);
+}
+
+int bilateral_shiftable_train(const float *img, int H, int W, int radius, float sigma_r, float T,
+                              const bsk_options *opt, float *out, float *saved, void *stream)
+{
+    if (!img || !out || !saved) return fail(BSK_EINVAL, "null pointer");
+    Resolved r;
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r);
+    if (st) return st;
+    if (r.prec != BSK_FP32 || r.kahan)
+        return fail(BSK_EUNSUPPORTED, "the training forward is FP32 without compensation");
+    if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "training forward needs dense pitch");
+    const size_t n = (size_t)H * W * 4;
+    if (overlap(img, n, out, n) || overlap(img, n, saved, 3 * n) || overlap(out, n, saved, 3 * n))
+        return fail(BSK_EINVAL, "buffers overlap");
+    return train_impl(img, H, W, r, out, saved, stream);
+}
+
+int bilateral_shiftable_backward(const float *img, const float *grad_out, const float *out, const float *saved,
+                                 int H, int W, int radius, float sigma_r, float T, const bsk_options *opt,
+                                 float *grad_img, float *grad_sigma, void *stream)
+{
+    if (!img || !grad_out) return fail(BSK_EINVAL, "null pointer");
+    if ((out == nullptr) != (saved == nullptr)) return fail(BSK_EINVAL, "out and saved must both be given or both NULL");
+    Resolved r;
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r);
+    if (st) return st;
+    if (r.prec != BSK_FP32 || r.kahan) return fail(BSK_EUNSUPPORTED, "the adjoint is FP32");
+    if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "the adjoint needs dense pitch");
+    const size_t n = (size_t)H * W * 4;
+    if (grad_img && (overlap(grad_img, n, img, n) || overlap(grad_img, n, grad_out, n)))
+        return fail(BSK_EINVAL, "grad_img overlaps an input");
+    if (!grad_img && !grad_sigma) return BSK_OK;
+
+    if (!out) {
+        void *tmp = nullptr;
+        st = get_ws(stream, 2, 4 * n, &tmp);
+        if (st) return st;
+        float *u = (float *)tmp;
+        float *sv = u + (size_t)H * W;
+        st = train_impl(img, H, W, r, u, sv, stream);
+        if (st) return st;
+        out = u;
+        saved = sv;
+    }
+    bsk::StripArgs a;
+    fill_args(&a, r, H, W);
+    a.io.img = img;
+    a.io.aux0 = grad_out;
+    a.io.aux1 = saved;                      // Q
+    a.io.aux2 = out;                        // u
+    a.io.aux3 = saved + (size_t)H * W;      // E1
+    a.io.aux4 = saved + 2 * (size_t)H * W;  // E2
+    a.io.out = grad_img;
+    const int nred = nblocks(r, H, W);
+    void *red = nullptr;
+    st = get_ws(stream, 3, (size_t)nred * sizeof(double), &red);
+    if (st) return st;
+    a.red = (double *)red;
+    if (r.plan.K > bsk::chunk_backward_f32(r.block)) {
+        void *ws = nullptr;
+        st = get_ws(stream, 4, (size_t)bsk::acc_count_backward() * H * W * 4, &ws);
+        if (st) return st;
+        a.ws = ws;
+    }
+    hipError_t e = bsk::launch_backward_f32(a, r.block, grad_sigma, 1.0 / (double)sigma_r, nred,
+                                            (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return BSK_OK;
+}
+
+int bsk_order_for(float sigma_r, float T)
+{
+    if (!finite_pos(sigma_r) || !finite_pos(T)) return fail(-1, "sigma_r and T must be finite and > 0");
+    const double x = 2.0 * (double)T / (M_PI * (double)sigma_r);
+    if (!(x * x < 2e9)) return fail(-1, "order too large");
+    return bsk::order_for(sigma_r, T);
+}
+
+int bsk_plan_info(int N, double eps, int *K, double *dropped)
+{
+    if (N < 0 || N > 1000000) return fail(BSK_EINVAL, "N out of range");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BSK_EINVAL, "eps must be finite and >= 0");
+    bsk::plan_counts(N, eps, K, dropped);
+    return BSK_OK;
+}
+
+double bsk_truncation_error(int N, double eps)
+{
+    double d = 0.0;
+    if (bsk_plan_info(N, eps, nullptr, &d) != BSK_OK) return -1.0;
+    return d;
+}
+
+const char *bsk_last_error(void) { return g_err; }
+
+void bsk_release_batched(void);
+
+int bsk_release(void)
+{
+    bsk_release_batched();
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    hipError_t e = hipDeviceSynchronize();
+    for (auto &kv : g_ws) {
+        if (kv.second.ptr) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(kv.first.dev);
+            hipFree(kv.second.ptr);
+            (void)hipSetDevice(cur);
+        }
+    }
+    g_ws.clear();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    return BSK_OK;
+}
+
+const char *bsk_version(void) { return "bsk 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+// Batched entry points and the autotuner are implemented in bsk_batched.cpp.

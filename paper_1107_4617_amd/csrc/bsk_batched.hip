@@ -1,0 +1,81 @@
+// Persistent batched kernel: many images of different sizes, radii and
+// sigma_r in one launch.  Each workgroup repeatedly claims a work unit
+// (image, strip, row segment) from a device counter and runs the same fused
+// strip body as the single-image forward kernel on it; the loop ends for
+// every workgroup once the counter passes the last unit, so the grid always
+// drains.  Units are numbered image by image in the order of the host table,
+// which lists the most expensive images first.
+#include "bsk_device.h"
+
+namespace bsk {
+
+constexpr int kc_batched(int block) { return block == 256 ? 16 : block == 512 ? 8 : 4; }
+int chunk_batched_f32(int block) { return kc_batched(block); }
+int max_radius_batched(int block) { return (block - 2) / 2; }
+
+__global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
+
+template <int BLOCK, int KC>
+__global__ void __launch_bounds__(BLOCK, 1) batched_kernel(const BatchArgs a)
+{
+    constexpr int ROWS = PolForward<float>::NCH * KC;
+    __shared__ float lds[2 * ROWS * (BLOCK + 1)];
+    __shared__ int unit_sh;
+    for (;;) {
+        if (threadIdx.x == 0) unit_sh = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int unit = unit_sh;
+        __syncthreads();
+        if (unit >= a.total_units) break;
+        // image owning this unit: last entry with unit0 <= unit
+        int lo = 0, hi = a.nimg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.imgs[mid].unit0 <= unit) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchImage im = a.imgs[lo];
+        const int local = unit - im.unit0;
+        const int bx = local % im.strips;
+        const int by = local / im.strips;
+        IO io;
+        io.img = im.img;
+        io.aux0 = io.aux1 = io.aux2 = io.aux3 = io.aux4 = nullptr;
+        io.out = im.out;
+        io.out2 = nullptr;
+        io.H = im.H;
+        io.W = im.W;
+        io.pitch_in = im.W;
+        io.pitch_out = im.W;
+        Geom gm;
+        gm.H = im.H;
+        gm.W = im.W;
+        gm.pitch_in = im.W;
+        gm.pitch_out = im.W;
+        gm.rh = im.rh;
+        gm.rv = im.rv;
+        gm.S = im.S;
+        gm.K = im.K;
+        gm.omega_base = im.omega_base;
+        gm.delta = im.delta;
+        gm.v = a.vtab + im.v_off;
+        gm.ws = im.ws_off >= 0 ? (void *)(a.ws + im.ws_off) : nullptr;
+        strip_body<float, BLOCK, KC, PolForward<float>, 0, false>(io, gm, bx, by, lds, nullptr, nullptr);
+    }
+}
+
+hipError_t launch_batched_f32(const BatchArgs &a, int block, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (block) {
+    case 256: hipLaunchKernelGGL((batched_kernel<256, kc_batched(256)>), dim3(grid), dim3(256), 0, s, a); break;
+    case 512: hipLaunchKernelGGL((batched_kernel<512, kc_batched(512)>), dim3(grid), dim3(512), 0, s, a); break;
+    case 1024: hipLaunchKernelGGL((batched_kernel<1024, kc_batched(1024)>), dim3(grid), dim3(1024), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bsk

@@ -1,0 +1,39 @@
+// Host-side helpers shared by the C ABI translation units of libbsk.
+#pragma once
+
+#include "../../include/bsk.h"
+#include "bsk_internal.h"
+
+namespace bsk {
+namespace host {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+// Grow-only device buffer per (device, stream, slot).
+int get_ws(void *stream, int slot, size_t bytes, void **out);
+int device_cus();
+bool finite_pos(double x);
+
+// A validated single-image request: order, plan, clamped radii, launch shape.
+struct Resolved {
+    int N;
+    int prec;
+    int kahan;
+    int pitch_in, pitch_out;
+    int rh, rv;
+    int block;
+    int S;
+    bsk::Plan plan;
+};
+
+int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r);
+void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W);
+int nblocks(const Resolved &r, int H, int W);
+bool overlap(const void *a, size_t na, const void *b, size_t nb);
+
+// Tuned launch shape for a single-image forward request, if the autotuner has
+// measured one for this (radius, orders, H, W, precision); returns false if not.
+bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S);
+
+}  // namespace host
+}  // namespace bsk

@@ -1,0 +1,106 @@
+// Internal declarations shared by the host API and the HIP kernels of libbsk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bsk {
+
+constexpr int kMaxOrders = 256;   // folded orders carried in kernel arguments
+
+// Folded plan of the raised-cosine range kernel (Section 3, q_N, eq. (6)).
+// The unfolded expansion cos^N(a) = 2^-N sum_n C(N,n) cos((2n-N) a) pairs
+// term n with term N-n (same weight, opposite frequency); after folding, the
+// m-th order has frequency omega(m) = omega_base + m * delta (in units of the
+// image value) and weight v[m]: twice the unfolded weight, except the zero
+// frequency term of even N.  Orders are listed from the lowest frequency
+// (largest weight) outwards, so truncation keeps a prefix m < K.
+struct Plan {
+    int N = 0;
+    int K = 0;               // folded orders kept
+    int K_full = 0;          // folded orders before truncation
+    double gamma = 0.0;      // 1 / sigma_r
+    double omega_base = 0.0; // omega(0)
+    double delta = 0.0;      // omega(m+1) - omega(m)
+    double dropped = 0.0;    // unfolded weight mass removed by truncation
+    double v[kMaxOrders];    // folded weights (FP64)
+};
+
+// Builds the plan; returns 0, or -2 if more than kMaxOrders orders remain.
+int make_plan(int N, double sigma_r, double eps, Plan *p);
+int order_for(double sigma_r, double T);
+// Full folded-order count and dropped mass without the kMaxOrders limit.
+void plan_counts(int N, double eps, int *K, double *dropped);
+
+// Buffers and layout of one image as the kernel policies see them.
+struct IO {
+    const void *img;       // f, float or double, pitch_in elements per row
+    const float *aux0;     // backward: dL/dout
+    const float *aux1;     // backward: saved Q
+    const float *aux2;     // backward: out u
+    const float *aux3;     // backward: saved E1
+    const float *aux4;     // backward: saved E2
+    void *out;             // main output (float or double), pitch_out elements per row
+    float *out2;           // train: saved planes Q, E1, E2 (dense)
+    int H, W;
+    int pitch_in, pitch_out;
+};
+
+// Per-launch arguments of the single-image strip kernels.  Weights are FP64 in
+// the argument block; each kernel converts them to its accumulation type.
+struct StripArgs {
+    IO io;
+    void *ws;              // partial accumulators across order chunks (NACC planes) or null
+    double *red;           // backward: per-workgroup partial sums for d/dsigma_r
+    int rh, rv;            // clamped horizontal / vertical radii
+    int S;                 // output rows per workgroup
+    int K;                 // folded orders
+    int strips;            // workgroups across the width
+    double omega_base, delta;
+    double v[kMaxOrders];
+};
+
+// Launch helpers implemented in bsk_kernels.hip.  `prec` selects the stack
+// quantisation (bsk_precision) for the FP32 kernels.
+hipError_t launch_forward_f32(const StripArgs &a, int block, int prec, int kahan, hipStream_t s);
+hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s);
+hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s);
+hipError_t launch_backward_f32(const StripArgs &a, int block, float *grad_sigma, double inv_sigma,
+                               int nred, hipStream_t s);
+
+// Orders per chunk (one pass of the strip kernel) for a kernel family/block.
+int chunk_forward_f32(int block);
+int chunk_forward_f64(int block);
+int chunk_train_f32(int block);
+int chunk_backward_f32(int block);
+int acc_count_forward();   // accumulators per pixel kept across chunks
+int acc_count_train();
+int acc_count_backward();
+
+// ----------------------------------------------------------------- batched --
+struct BatchImage {
+    const float *img;
+    float *out;
+    int H, W, rh, rv, S, K;
+    int strips;
+    int unit0;               // first work unit of this image
+    long long ws_off;        // offset of this image's accumulator planes in ws, -1 if none
+    int v_off;               // offset of this image's weights in the weight table
+    double omega_base, delta;
+};
+
+struct BatchArgs {
+    const BatchImage *imgs;  // device table, ordered by unit0
+    const double *vtab;      // device folded weights
+    float *ws;               // partial accumulators for images with K > chunk
+    int nimg;
+    int total_units;
+    unsigned *counter;       // device work counter, zeroed by a kernel before each launch
+};
+
+hipError_t launch_batched_f32(const BatchArgs &a, int block, int grid, hipStream_t s);
+int chunk_batched_f32(int block);
+// Largest clamped radius the batched kernel of a given block size accepts.
+int max_radius_batched(int block);
+
+}  // namespace bsk

@@ -1,0 +1,226 @@
+"""PyTorch-facing calls of the shiftable bilateral filter.
+
+PyTorch provides device memory and the current stream; every arithmetic step
+runs in libbsk's HIP kernels through the C ABI (include/bsk.h).  Tensors must
+be 2-D, contiguous and on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+
+__all__ = ["bilateral", "bilateral_train", "bilateral_backward", "bilateral_batched", "order_for",
+           "plan_info", "autotune", "BilateralFunction", "ShiftableBilateral", "release"]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_image(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor (libbsk runs only on the GPU)")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D (H, W), got shape {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, strip_h=0):
+    o = _lib.Options()
+    if N is None:
+        o.order_mode = 0
+        o.N = 0
+    else:
+        o.order_mode = 1
+        o.N = int(N)
+    o.precision = _lib.PRECISIONS[precision]
+    o.weight_eps = float(weight_eps)
+    o.kahan = 1 if kahan else 0
+    o.block = int(block)
+    o.strip_h = int(strip_h)
+    return o
+
+
+def order_for(sigma_r: float, T: float = 255.0) -> int:
+    """N_0: smallest order making the kernel non-negative and unimodal on [-T, T]."""
+    n = _lib.load().bsk_order_for(float(sigma_r), float(T))
+    if n < 0:
+        _lib.check(_lib.BSK_EINVAL)
+    return n
+
+
+def plan_info(N: int, eps: float = 0.0):
+    """(folded orders kept, dropped unfolded weight mass) for order N and threshold eps."""
+    K = ctypes.c_int(0)
+    d = ctypes.c_double(0.0)
+    _lib.check(_lib.load().bsk_plan_info(int(N), float(eps), ctypes.byref(K), ctypes.byref(d)))
+    return K.value, d.value
+
+
+def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,
+              precision: str = "fp32", weight_eps: float = 0.0, kahan: bool = False, block: int = 0,
+              strip_h: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Bilateral filter with a (2r+1)^2 box window and the range kernel cos^N(t / (sigma_r sqrt N)).
+
+    precision: "fp32" (default); "bf16", "fp16" or "i16" (precision form: the cos/sin stack
+    quantised to bfloat16, float16 or 16-bit fixed point, FP32 sums); "fp64" (img float64).
+    N: None selects N_0(sigma_r, T).  weight_eps > 0 drops binomial weights below it.
+    """
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    _check_image(img, "img", dt)
+    if out is None:
+        out = torch.empty_like(img)
+    else:
+        _check_image(out, "out", dt)
+        if out.shape != img.shape:
+            raise ValueError("out has the wrong shape")
+    H, W = img.shape
+    opt = _options(N, precision, weight_eps, kahan, block, strip_h)
+    with torch.cuda.device(img.device):
+        _lib.check(_lib.load().bilateral_shiftable_ex(
+            ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),
+            ctypes.c_void_p(out.data_ptr()), ctypes.byref(opt), _stream()))
+    return out
+
+
+def bilateral_train(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None):
+    """(out, saved) where saved is (3, H, W): Q, E1, E2 for the adjoint."""
+    _check_image(img, "img")
+    H, W = img.shape
+    out = torch.empty_like(img)
+    saved = torch.empty((3, H, W), dtype=torch.float32, device=img.device)
+    opt = _options(N)
+    with torch.cuda.device(img.device):
+        _lib.check(_lib.load().bilateral_shiftable_train(
+            ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T), ctypes.byref(opt),
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(saved.data_ptr()), _stream()))
+    return out, saved
+
+
+def bilateral_backward(img: torch.Tensor, grad_out: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0,
+                       N: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                       saved: Optional[torch.Tensor] = None, need_img: bool = True, need_sigma: bool = True):
+    """(dL/dimg or None, dL/dsigma_r as a 0-d tensor or None)."""
+    _check_image(img, "img")
+    _check_image(grad_out, "grad_out")
+    H, W = img.shape
+    if (out is None) != (saved is None):
+        raise ValueError("give both out and saved, or neither")
+    if out is not None:
+        _check_image(out, "out")
+        if saved.shape != (3, H, W) or not saved.is_contiguous() or saved.dtype != torch.float32:
+            raise ValueError("saved must be a contiguous float32 (3, H, W) tensor")
+    gi = torch.empty_like(img) if need_img else None
+    gs = torch.empty((), dtype=torch.float32, device=img.device) if need_sigma else None
+    opt = _options(N)
+    p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+    with torch.cuda.device(img.device):
+        _lib.check(_lib.load().bilateral_shiftable_backward(
+            p(img), p(grad_out), p(out), p(saved), H, W, int(radius), float(sigma_r), float(T),
+            ctypes.byref(opt), p(gi), p(gs), _stream()))
+    return gi, gs
+
+
+def bilateral_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas: Sequence[float],
+                      T: float = 255.0, Ns: Optional[Sequence[int]] = None, outs=None,
+                      graph_key: Optional[int] = None, strip_h: int = 0):
+    """Filters many images (any sizes, radii, sigma_r) in one persistent launch.
+
+    With graph_key set, the first call captures the launch into a HIP graph on the
+    current (non-default) stream and later calls with the same key replay it."""
+    B = len(imgs)
+    if outs is None:
+        outs = [torch.empty_like(x) for x in imgs]
+    descs = (_lib.ImageDesc * B)()
+    for b, (x, o) in enumerate(zip(imgs, outs)):
+        _check_image(x, f"imgs[{b}]")
+        _check_image(o, f"outs[{b}]")
+        descs[b].img = x.data_ptr()
+        descs[b].out = o.data_ptr()
+        descs[b].H, descs[b].W = x.shape
+        descs[b].radius = int(radii[b])
+        descs[b].sigma_r = float(sigmas[b])
+        descs[b].N = -1 if Ns is None or Ns[b] is None else int(Ns[b])
+    opt = _options(strip_h=strip_h)
+    lib = _lib.load()
+    with torch.cuda.device(imgs[0].device):
+        if graph_key is None:
+            _lib.check(lib.bilateral_shiftable_batched(descs, B, float(T), ctypes.byref(opt), _stream()))
+        else:
+            _lib.check(lib.bilateral_shiftable_batched_graph(descs, B, float(T), ctypes.byref(opt), int(graph_key),
+                                                             _stream()))
+    return outs
+
+
+def autotune(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,
+             precision: str = "fp32", weight_eps: float = 0.0, kahan: bool = False, path: Optional[str] = None):
+    """Times the launch shapes for this request and caches the fastest; returns (block, rows, ms)."""
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    _check_image(img, "img", dt)
+    out = torch.empty_like(img)
+    H, W = img.shape
+    opt = _options(N, precision, weight_eps, kahan)
+    b, s, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+    with torch.cuda.device(img.device):
+        _lib.check(_lib.load().bsk_autotune(
+            ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),
+            ctypes.c_void_p(out.data_ptr()), ctypes.byref(opt), path.encode() if path else None, _stream(),
+            ctypes.byref(b), ctypes.byref(s), ctypes.byref(ms)))
+    return b.value, s.value, ms.value
+
+
+def release():
+    _lib.check(_lib.load().bsk_release())
+
+
+class BilateralFunction(torch.autograd.Function):
+    """Autograd wrapper: forward saves (out, Q, E1, E2); backward runs the adjoint kernel.
+
+    sigma_r is a 0-d tensor (learnable); the order N stays fixed (an integer)."""
+
+    @staticmethod
+    def forward(ctx, img, sigma_r, radius: int, T: float, N: int):
+        s = float(sigma_r.detach())
+        out, saved = bilateral_train(img.detach(), radius, s, T, N)
+        ctx.save_for_backward(img, out, saved)
+        ctx.params = (radius, s, T, N)
+        ctx.sigma_dtype = sigma_r.dtype
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        img, out, saved = ctx.saved_tensors
+        radius, s, T, N = ctx.params
+        need_img, need_sigma = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gi, gs = bilateral_backward(img, grad_out.contiguous(), radius, s, T, N, out=out, saved=saved,
+                                    need_img=need_img, need_sigma=need_sigma)
+        if gs is not None:
+            gs = gs.to(ctx.sigma_dtype)
+        return gi, gs, None, None, None
+
+
+class ShiftableBilateral(torch.nn.Module):
+    """Bilateral filter layer with a learnable range scale sigma_r and a fixed order N."""
+
+    def __init__(self, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None):
+        super().__init__()
+        self.radius = int(radius)
+        self.T = float(T)
+        self.N = int(N) if N is not None else order_for(sigma_r, T)
+        self.sigma_r = torch.nn.Parameter(torch.tensor(float(sigma_r)))
+
+    def forward(self, img: torch.Tensor) -> torch.Tensor:
+        if img.dim() == 2:
+            return BilateralFunction.apply(img, self.sigma_r, self.radius, self.T, self.N)
+        return torch.stack([BilateralFunction.apply(x, self.sigma_r, self.radius, self.T, self.N)
+                            for x in img.reshape(-1, *img.shape[-2:])]).reshape(img.shape)

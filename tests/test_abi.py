@@ -1,0 +1,177 @@
+"""Host-side tests of libbsk (no GPU needed): exports, planning, argument validation."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1107_4617_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "bsk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _header_functions()
+    assert "bilateral_shiftable" in names and "bilateral_shiftable_batched" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_lib.EXPORTS)
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.bsk_version()
+
+
+@pytest.mark.parametrize("sigma,expect", [(30.0, 30), (25.0, 43), (15.0, 118), (10.0, 264), (60.0, 8)])
+def test_order_for(lib, sigma, expect):
+    assert lib.bsk_order_for(sigma, 255.0) == expect
+
+
+def test_order_for_rejects_bad_input(lib):
+    assert lib.bsk_order_for(0.0, 255.0) == -1
+    assert lib.bsk_order_for(float("nan"), 255.0) == -1
+    assert lib.bsk_order_for(30.0, -1.0) == -1
+
+
+@pytest.mark.parametrize("N,eps", [(0, 0.0), (1, 0.0), (2, 0.0), (30, 0.0), (30, 1e-7), (117, 1e-7), (264, 1e-7),
+                                   (43, 1e-4), (117, 0.0), (511, 0.0)])
+def test_plan_counts_match_exact_binomials(lib, N, eps):
+    """Folded orders kept and dropped mass against exact integer binomials."""
+    K = ctypes.c_int(0)
+    d = ctypes.c_double(0.0)
+    assert lib.bsk_plan_info(N, eps, ctypes.byref(K), ctypes.byref(d)) == 0
+    w = [math.comb(N, n) / 2 ** N for n in range(N + 1)]
+    kept = [n for n in range(N + 1) if not (eps > 0 and w[n] < eps)]
+    folded = len([n for n in kept if 2 * n <= N])   # one folded order per pair (and the centre)
+    assert K.value == folded
+    drop = math.fsum(w[n] for n in range(N + 1) if eps > 0 and w[n] < eps)
+    assert abs(d.value - drop) <= 1e-12 * max(drop, 1e-300) + 1e-300
+    assert abs(lib.bsk_truncation_error(N, eps) - drop) <= 1e-12 * max(drop, 1e-300) + 1e-300
+
+
+def test_truncation_table():
+    from paper_1107_4617_amd import plan_info
+    for N, K, eps in [(117, 28, 1.283e-7), (30, 14, 5.8e-8), (264, 42, 2.6e-7)]:
+        k, d = plan_info(N, 1e-7)
+        assert k == K and abs(d - eps) / eps < 0.01
+
+
+def _call_ex(lib, img=1, H=8, W=8, r=2, s=30.0, T=255.0, out=2, opt=None):
+    o = opt if opt is not None else _lib.Options()
+    return lib.bilateral_shiftable_ex(ctypes.c_void_p(img), H, W, r, s, T, ctypes.c_void_p(out),
+                                      ctypes.byref(o), None)
+
+
+def test_argument_errors(lib):
+    E = _lib.BSK_EINVAL
+    big = 1 << 40
+    assert _call_ex(lib, img=0) == E
+    assert _call_ex(lib, out=0) == E
+    assert _call_ex(lib, img=big, out=big) == E        # img == out
+    assert _call_ex(lib, img=big, out=big + 8) == E    # overlapping rows
+    assert b"overlap" in lib.bsk_last_error()
+    assert _call_ex(lib, H=0) == E
+    assert _call_ex(lib, W=-3) == E
+    assert _call_ex(lib, r=-1) == E
+    assert _call_ex(lib, s=0.0) == E
+    assert _call_ex(lib, s=float("nan")) == E
+    assert _call_ex(lib, s=float("inf")) == E
+    assert _call_ex(lib, T=0.0) == E
+    assert b"T must be" in lib.bsk_last_error()
+    o = _lib.Options()
+    o.order_mode = 1
+    o.N = -2
+    assert _call_ex(lib, opt=o) == E
+    o = _lib.Options()
+    o.precision = 9
+    assert _call_ex(lib, opt=o) == E
+    o = _lib.Options()
+    o.weight_eps = -1.0
+    assert _call_ex(lib, opt=o) == E
+    o = _lib.Options()
+    o.pitch_in = 3
+    assert _call_ex(lib, opt=o) == E
+    o = _lib.Options()
+    o.block = 300
+    assert _call_ex(lib, opt=o) == E
+    o = _lib.Options()
+    o.order_mode = 2
+    assert _call_ex(lib, opt=o) == E
+
+
+def test_range_and_unsupported_errors(lib):
+    o = _lib.Options()
+    o.order_mode = 1
+    o.N = 2000          # 1001 folded orders > BSK_MAX_ORDERS
+    assert _call_ex(lib, img=1 << 40, out=1 << 41, opt=o) == _lib.BSK_ERANGE
+    o.weight_eps = 1e-7  # truncation brings it back under the limit
+    K = ctypes.c_int(0)
+    lib.bsk_plan_info(2000, 1e-7, ctypes.byref(K), None)
+    assert K.value <= 256
+    assert _call_ex(lib, img=1 << 40, out=1 << 41, H=2000, W=2000, r=600) == _lib.BSK_EUNSUPPORTED
+    o = _lib.Options()
+    o.block = 256
+    assert _call_ex(lib, img=1 << 40, out=1 << 41, H=300, W=300, r=200, opt=o) == _lib.BSK_EUNSUPPORTED
+
+
+def test_train_and_backward_validation(lib):
+    o = _lib.Options()
+    vp = ctypes.c_void_p
+    assert lib.bilateral_shiftable_train(None, 8, 8, 2, 30.0, 255.0, ctypes.byref(o), vp(1), vp(2), None) == -1
+    o.precision = _lib.BSK_BF16
+    assert lib.bilateral_shiftable_train(vp(1 << 40), 8, 8, 2, 30.0, 255.0, ctypes.byref(o), vp(1 << 41),
+                                         vp(1 << 42), None) == _lib.BSK_EUNSUPPORTED
+    o = _lib.Options()
+    # out given without saved
+    assert lib.bilateral_shiftable_backward(vp(1 << 40), vp(1 << 41), vp(1 << 42), None, 8, 8, 2, 30.0, 255.0,
+                                            ctypes.byref(o), vp(1 << 43), None, None) == -1
+    # nothing requested: no work, success
+    assert lib.bilateral_shiftable_backward(vp(1 << 40), vp(1 << 41), None, None, 8, 8, 2, 30.0, 255.0,
+                                            ctypes.byref(o), None, None, None) == 0
+
+
+def test_batched_validation(lib):
+    d = (_lib.ImageDesc * 2)()
+    for b in range(2):
+        d[b].img = (1 << 40) + b * (1 << 30)
+        d[b].out = (1 << 41) + b * (1 << 30)
+        d[b].H, d[b].W, d[b].radius, d[b].sigma_r, d[b].N = 16, 16, 2, 30.0, -1
+    o = _lib.Options()
+    d[1].sigma_r = -1.0
+    assert lib.bilateral_shiftable_batched(d, 2, 255.0, ctypes.byref(o), None) == -1
+    d[1].sigma_r = 30.0
+    d[0].out = d[0].img
+    assert lib.bilateral_shiftable_batched(d, 2, 255.0, ctypes.byref(o), None) == -1
+    assert lib.bilateral_shiftable_batched(d, 0, 255.0, ctypes.byref(o), None) == -1
+    assert lib.bilateral_shiftable_batched_graph(d, 2, 255.0, ctypes.byref(o), 7, None) == -1  # default stream
+
+
+def _no_device():
+    import torch
+    return torch.cuda.device_count() == 0
+
+
+@pytest.mark.skipif(not _no_device(), reason="checks the no-device error path; a GPU is present")
+def test_no_device_reports_hip_error(lib):
+    assert _call_ex(lib, img=1 << 40, out=1 << 41) == _lib.BSK_EHIP
+    assert len(lib.bsk_last_error()) > 0
+
+
+def test_python_layer_rejects_cpu_tensors():
+    import torch
+    from paper_1107_4617_amd import bilateral
+    with pytest.raises(TypeError):
+        bilateral(torch.zeros(4, 4), 1, 30.0)

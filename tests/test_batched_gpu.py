@@ -1,0 +1,77 @@
+"""Batched persistent launch (and its HIP-graph replay) against the single-image path
+and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1107_4617_amd import bilateral, bilateral_batched, order_for
+from paper_1107_4617_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+T = 255.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+
+
+def _batch(n, seed, lo=20, hi=300):
+    specs = wl.batch_specs(n, seed=seed, side_lo=lo, side_hi=hi)
+    imgs = [torch.from_numpy(wl.gradient_image(H, W, s)).cuda() for (H, W, r, sg, s) in specs]
+    return specs, imgs
+
+
+def test_batched_equals_single_image_path_and_oracle():
+    specs, imgs = _batch(14, seed=41)
+    outs = bilateral_batched(imgs, [s[2] for s in specs], [s[3] for s in specs], T)
+    torch.cuda.synchronize()
+    for (H, W, r, sg, _), x, y in zip(specs, imgs, outs):
+        # same launch shape (256 lanes, 64-row units) gives the same arithmetic
+        single = bilateral(x, r, sg, T, block=256, strip_h=64)
+        torch.cuda.synchronize()
+        assert torch.equal(single, y)
+    for b in (0, 5, 13):
+        H, W, r, sg, _ = specs[b]
+        ref = oracle.bilateral(imgs[b].cpu().numpy(), r, sg, order_for(sg, T))
+        assert np.max(np.abs(outs[b].cpu().numpy() - ref)) <= 1e-4 * T
+
+
+def test_graph_replay_matches_eager():
+    specs, imgs = _batch(9, seed=42)
+    radii, sig = [s[2] for s in specs], [s[3] for s in specs]
+    eager = [t.clone() for t in bilateral_batched(imgs, radii, sig, T)]
+    stream = torch.cuda.Stream()
+    outs = [torch.empty_like(x) for x in imgs]
+    with torch.cuda.stream(stream):
+        for rep in range(4):
+            for o in outs:
+                o.fill_(-1.0)
+            bilateral_batched(imgs, radii, sig, T, outs=outs, graph_key=1001)
+            stream.synchronize()
+            for e, o in zip(eager, outs):
+                assert torch.equal(e, o), rep
+            # unrelated eager work between replays
+            bilateral(imgs[0], 3, 20.0, T)
+            stream.synchronize()
+
+
+def test_full_batch_256_images():
+    """256 images with sides U{128..2048}, sigma_r U[10, 60], r U{3..25}, N = N_0."""
+    specs = wl.batch_specs(256, seed=4)
+    imgs = [torch.from_numpy(wl.gradient_image(H, W, s)).cuda() for (H, W, r, sg, s) in specs]
+    radii, sig = [s[2] for s in specs], [s[3] for s in specs]
+    outs = bilateral_batched(imgs, radii, sig, T)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    for b in rng.choice(256, 6, replace=False):
+        H, W, r, sg, _ = specs[b]
+        single = bilateral(imgs[b], r, sg, T, block=256, strip_h=64)
+        torch.cuda.synchronize()
+        assert torch.equal(single, outs[b])
+        f = imgs[b].cpu().numpy()
+        idx = rng.integers(0, H * W, 400)
+        ref = oracle.bilateral_at(f, idx, r, sg, order_for(sg, T))
+        assert np.max(np.abs(outs[b].cpu().numpy().ravel()[idx] - ref)) <= 1e-4 * T

@@ -1,0 +1,197 @@
+"""Forward parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (max-abs over compared pixels): FP64 path 1e-9 T, FP32 path 1e-4 T,
+BF16/FP16 precision form 2e-3 T, with T = 255 the range bound.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1107_4617_amd import bilateral, order_for, plan_info
+from paper_1107_4617_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+T = 255.0
+TOL32 = 1e-4 * T
+TOL64 = 1e-9 * T
+TOL16 = 2e-3 * T
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+
+
+def _gpu_filter(f, r, s, N=None, **kw):
+    dt = torch.float64 if kw.get("precision") == "fp64" else torch.float32
+    x = torch.from_numpy(np.ascontiguousarray(f)).to(dtype=dt, device="cuda")
+    y = bilateral(x, r, s, T, N=N, **kw)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64)
+
+
+def _sample_idx(H, W, n, seed, extra_rows=(), extra_cols=()):
+    rng = np.random.default_rng(seed)
+    idx = set(rng.integers(0, H * W, n).tolist())
+    rows = {0, 1, H - 2, H - 1, *[x for x in extra_rows if 0 <= x < H]}
+    cols = {0, 1, W - 2, W - 1, *[x for x in extra_cols if 0 <= x < W]}
+    for i in rows:
+        for j in rng.integers(0, W, 64):
+            idx.add(i * W + int(j))
+    for j in cols:
+        for i in rng.integers(0, H, 64):
+            idx.add(int(i) * W + j)
+    return np.array(sorted(idx), dtype=np.int64)
+
+
+def test_smooth256_fp64_and_fp32():
+    """256x256 smooth+noise image, r=5, sigma_r=30, N=30; full-image comparison."""
+    f = wl.smooth_image(256, 256, 1)
+    ref = oracle.bilateral(f, 5, 30.0, 30)
+    out64 = _gpu_filter(f.astype(np.float64), 5, 30.0, N=30, precision="fp64")
+    assert np.max(np.abs(out64 - ref)) <= TOL64
+    out32 = _gpu_filter(f, 5, 30.0, N=30)
+    err = np.max(np.abs(out32 - ref))
+    assert err <= TOL32, err
+
+
+@pytest.mark.parametrize("shape,r,N,sigma,block,strip_h", [
+    ((1, 1), 3, 30, 30.0, 0, 0),
+    ((1, 37), 4, 30, 30.0, 0, 0),
+    ((41, 1), 4, 30, 30.0, 0, 0),
+    ((7, 300), 9, 30, 30.0, 0, 0),          # H < 2r+1
+    ((300, 500), 7, 30, 30.0, 256, 16),     # many strips and segments, ragged tails
+    ((129, 257), 20, 30, 30.0, 256, 33),
+    ((64, 64), 200, 30, 30.0, 0, 0),        # radius beyond the image: whole-image windows
+    ((50, 70), 0, 30, 30.0, 0, 0),          # r = 0: identity
+    ((60, 90), 6, 0, 30.0, 0, 0),           # N = 0: box mean
+    ((60, 90), 6, 1, 200.0, 0, 0),          # N = 1 (N_0 = 1 at sigma_r = 200)
+    ((60, 90), 6, 7, 70.0, 0, 0),           # odd N (N_0 = 6 at sigma_r = 70)
+    ((60, 90), 6, 2, 120.0, 0, 0),          # N = 2
+    ((80, 600), 70, 30, 30.0, 512, 20),     # 512-lane strips
+    ((40, 1100), 200, 30, 30.0, 1024, 0),   # 1024-lane strips
+])
+def test_shapes_and_edge_cases(shape, r, N, sigma, block, strip_h):
+    """Orders at or above N_0(sigma_r, 255), where the kernel is a valid (non-negative) kernel."""
+    f = wl.random_image(*shape, seed=sum(shape) + r)
+    ref = oracle.bilateral(f, r, sigma, N)
+    out = _gpu_filter(f, r, sigma, N=N, block=block, strip_h=strip_h)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
+def test_radius_zero_is_exact_identity():
+    f = wl.random_image(33, 45, 3)
+    out = _gpu_filter(f, 0, 30.0, N=30)
+    assert np.max(np.abs(out - f)) <= 2e-5 * T
+
+
+def test_constant_image_is_fixed():
+    f = np.full((70, 90), 137.25, np.float32)
+    out = _gpu_filter(f, 8, 30.0, N=30)
+    assert np.max(np.abs(out - 137.25)) <= 1e-5 * T
+
+
+@pytest.mark.parametrize("N", [117, 264])
+def test_multi_pass_orders(N):
+    """More folded orders than one pass holds (N=117: 59 orders; N=264: 133)."""
+    sigma = 15.0 if N == 117 else 10.0
+    f = wl.rect_image(96, 200, seed=N, n_rect=12)
+    ref = oracle.bilateral(f, 6, sigma, N)
+    out = _gpu_filter(f, 6, sigma, N=N)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
+def test_pitch():
+    f = wl.random_image(40, 60, 5)
+    big = np.zeros((40, 80), np.float32)
+    big[:, :60] = f
+    x = torch.from_numpy(big).cuda()
+    y = torch.full((40, 96), -7.0, device="cuda")
+    from paper_1107_4617_amd import _lib
+    import ctypes
+    o = _lib.Options()
+    o.pitch_in, o.pitch_out = 80, 96
+    _lib.check(_lib.load().bilateral_shiftable_ex(ctypes.c_void_p(x.data_ptr()), 40, 60, 4, 30.0, T,
+                                                  ctypes.c_void_p(y.data_ptr()), ctypes.byref(o), None))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    ref = oracle.bilateral(f, 4, 30.0, 30)
+    assert np.max(np.abs(y[:, :60] - ref)) <= TOL32
+    assert np.all(y[:, 60:] == -7.0)
+
+
+def test_sync_entry_point():
+    from paper_1107_4617_amd import _lib
+    import ctypes
+    f = wl.random_image(50, 77, 6)
+    x = torch.from_numpy(f).cuda()
+    y = torch.empty_like(x)
+    _lib.check(_lib.load().bilateral_shiftable(ctypes.c_void_p(x.data_ptr()), 50, 77, 3, 30.0, T,
+                                               ctypes.c_void_p(y.data_ptr())))
+    ref = oracle.bilateral(f, 3, 30.0, order_for(30.0, T))
+    assert np.max(np.abs(y.cpu().numpy() - ref)) <= TOL32
+
+
+def test_deterministic():
+    f = wl.rect_image(300, 400, seed=9)
+    a = _gpu_filter(f, 11, 30.0)
+    b = _gpu_filter(f, 11, 30.0)
+    assert np.array_equal(a, b)
+
+
+def test_rect4096_r20_sampled():
+    """Full-size 4096x4096 rect image, r=20, sigma_r=30, N=30, in the launch shape the
+    benchmark uses; oracle on sampled pixels (random, borders, strip/segment edges)."""
+    f = wl.rect_image(4096, 4096, seed=2)
+    out = _gpu_filter(f, 20, 30.0, N=30)
+    Wt = 256 - 40
+    cols = [k * Wt + d for k in range(1, 4096 // Wt + 1) for d in (-1, 0)]
+    idx = _sample_idx(4096, 4096, 3000, 22, extra_cols=cols)
+    ref = oracle.bilateral_at(f, idx, 20, 30.0, 30)
+    err = np.abs(out.ravel()[idx] - ref)
+    assert np.max(err) <= TOL32, np.max(err)
+
+
+def test_precision_forms_rect4096_full_image():
+    """Headline workload (4096^2, r=20, sigma_r=30, N=30) with the stack held in 16 bits and
+    weights below 1e-7 dropped (14 of 16 folded orders): every pixel against the FP32 path,
+    which is itself within 1e-4 T of the oracle (sampled test above).  The 16-bit
+    fixed-point stack stays within 2e-3 T of the oracle everywhere; bfloat16 and float16
+    stacks do not (their error is largest where the normaliser is small) and are held to
+    looser regression bounds; the measured errors are recorded in the design notes."""
+    f = wl.rect_image(4096, 4096, seed=2)
+    out32 = _gpu_filter(f, 20, 30.0, N=30)
+    idx = _sample_idx(4096, 4096, 800, 44)
+    ref_t = oracle.bilateral_at(f, idx, 20, 30.0, 30, eps=1e-7, truncated=True)
+    bounds = {"i16": TOL16, "fp16": 8 * TOL16, "bf16": 32 * TOL16}
+    for prec, bound in bounds.items():
+        out = _gpu_filter(f, 20, 30.0, N=30, precision=prec, weight_eps=1e-7, kahan=True)
+        assert np.max(np.abs(out - out32)) <= bound - TOL32, prec
+        assert np.max(np.abs(out.ravel()[idx] - ref_t)) <= bound, prec
+
+
+def test_rect8192_r32_precision_form_sampled():
+    """8192x8192, r=32, sigma_r=15, N=117, weights below 1e-7 dropped (28 of 59 folded
+    orders), against the oracle's truncated kernel and the exact one.  The 16-bit
+    fixed-point stack meets 2e-3 T; bfloat16 and float16 stacks do not at this sigma_r
+    (normalisers fall to ~5) and are held to looser regression bounds."""
+    f = wl.rect_image(8192, 8192, seed=3)
+    K, eps = plan_info(117, 1e-7)
+    assert K == 28 and abs(eps - 1.283e-7) < 1e-9
+    idx = _sample_idx(8192, 8192, 600, 33)
+    ref_t = oracle.bilateral_at(f, idx, 32, 15.0, 117, eps=1e-7, truncated=True)
+    ref = oracle.bilateral_at(f, idx, 32, 15.0, 117)
+    # the truncation alone moves the result by far less than the tolerance
+    assert np.max(np.abs(ref - ref_t)) <= 1e-3
+    bounds = {"i16": TOL16, "fp16": 8 * TOL16, "bf16": 32 * TOL16}
+    for prec, bound in bounds.items():
+        out = _gpu_filter(f, 32, 15.0, N=117, precision=prec, weight_eps=1e-7, kahan=True)
+        err = np.max(np.abs(out.ravel()[idx] - ref_t))
+        assert err <= bound, (prec, err)
+    out32 = _gpu_filter(f, 32, 15.0, N=117)
+    assert np.max(np.abs(out32.ravel()[idx] - ref)) <= TOL32

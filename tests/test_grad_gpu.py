@@ -1,0 +1,109 @@
+"""Adjoint (d/d image, d/d sigma_r) of the HIP path against the FP64 oracle gradient.
+
+Tolerances: dL/dimg within 1e-3 of max |dL/dimg| (max-abs), dL/dsigma_r within
+1e-3 relative; the oracle gradient itself is pinned to central differences in
+the CPU tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1107_4617_amd import ShiftableBilateral, bilateral_backward, bilateral_train
+from paper_1107_4617_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+T = 255.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("shape,r,sigma,N,seed", [((40, 56), 3, 25.0, 43, 1), ((33, 70), 5, 30.0, 30, 2),
+                                                  ((64, 64), 10, 25.0, 43, 3), ((20, 300), 7, 40.0, 17, 4)])
+def test_adjoint_matches_oracle(shape, r, sigma, N, seed):
+    f = wl.rect_image(*shape, seed=seed, n_rect=6)
+    g = np.random.default_rng(seed).normal(size=shape)
+    gf_ref, gs_ref, u_ref = oracle.bilateral_grad(f.astype(np.float64), g, r, sigma, N)
+    x = _cuda(f)
+    out, saved = bilateral_train(x, r, sigma, T, N)
+    assert np.max(np.abs(out.cpu().numpy() - u_ref)) <= 1e-4 * T
+    _, _, Q = oracle.bilateral(f, r, sigma, N, return_pq=True)
+    assert np.max(np.abs(saved[0].cpu().numpy() - Q) / Q) <= 1e-4
+    gi, gs = bilateral_backward(x, _cuda(g), r, sigma, T, N, out=out, saved=saved)
+    torch.cuda.synchronize()
+    scale = np.max(np.abs(gf_ref))
+    assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * scale
+    assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
+    # recompute path (no saved state) gives the same numbers
+    gi2, gs2 = bilateral_backward(x, _cuda(g), r, sigma, T, N)
+    torch.cuda.synchronize()
+    assert torch.equal(gi, gi2) and torch.equal(gs, gs2)
+
+
+def test_denoise_crop_against_oracle_and_differences():
+    """Centre 32x32 crop of the first 1024x1024 denoising image (r=10, sigma_r=25, N=43),
+    treated as a standalone image; loss = mean((u - target)^2)."""
+    noisy, target = wl.denoise_pair(0)
+    c0 = 512 - 16
+    f = noisy[c0:c0 + 32, c0:c0 + 32].astype(np.float64)
+    tg = target[c0:c0 + 32, c0:c0 + 32].astype(np.float64)
+    r, s, N = 10, 25.0, 43
+    u = oracle.bilateral(f, r, s, N)
+    gbar = 2.0 * (u - tg) / u.size
+    gf_ref, gs_ref, _ = oracle.bilateral_grad(f, gbar, r, s, N)
+
+    def loss(ff, ss):
+        return float(np.mean((oracle.bilateral(ff, r, ss, N) - tg) ** 2))
+
+    h = 1e-3
+    fd_s = (loss(f, s + h) - loss(f, s - h)) / (2 * h)
+    assert abs(gs_ref - fd_s) <= 1e-6 * abs(fd_s)
+    x = _cuda(f)
+    layer = ShiftableBilateral(r, s, T, N).cuda()
+    xr = x.clone().requires_grad_(True)
+    out = layer(xr)
+    L = torch.mean((out - _cuda(tg)) ** 2)
+    L.backward()
+    torch.cuda.synchronize()
+    scale = np.max(np.abs(gf_ref))
+    assert np.max(np.abs(xr.grad.cpu().numpy() - gf_ref)) <= 1e-3 * scale
+    assert abs(float(layer.sigma_r.grad) - gs_ref) <= 1e-3 * abs(gs_ref)
+
+
+def test_denoise_256_crop():
+    noisy, _ = wl.denoise_pair(1)
+    f = noisy[300:556, 200:456]
+    g = np.random.default_rng(7).normal(size=f.shape)
+    gf_ref, gs_ref, _ = oracle.bilateral_grad(f.astype(np.float64), g, 10, 25.0, 43)
+    gi, gs = bilateral_backward(_cuda(f), _cuda(g), 10, 25.0, T, 43)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * np.max(np.abs(gf_ref))
+    assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
+
+
+def test_multi_pass_adjoint():
+    """N = 117: 59 folded orders, several passes in both training forward and adjoint."""
+    f = wl.rect_image(48, 80, seed=11, n_rect=8)
+    g = np.random.default_rng(11).normal(size=f.shape)
+    gf_ref, gs_ref, _ = oracle.bilateral_grad(f.astype(np.float64), g, 4, 15.0, 117)
+    gi, gs = bilateral_backward(_cuda(f), _cuda(g), 4, 15.0, T, 117)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * np.max(np.abs(gf_ref))
+    assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
+
+
+def test_adjoint_deterministic():
+    f = wl.rect_image(200, 300, seed=12)
+    g = np.random.default_rng(12).normal(size=f.shape)
+    a = bilateral_backward(_cuda(f), _cuda(g), 9, 25.0, T, 43)
+    b = bilateral_backward(_cuda(f), _cuda(g), 9, 25.0, T, 43)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
