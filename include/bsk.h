@@ -80,6 +80,8 @@ typedef struct {
     int pitch_out;        /* output row pitch in elements; 0 = W */
     int block;            /* lanes per workgroup (256, 512, 1024); 0 = auto */
     int strip_h;          /* output rows per workgroup; 0 = auto */
+    int order_chunk;      /* FP32 forward: orders per pass, the full or the half pass of the
+                             block (256: 16|8, 512: 8|4, 1024: 4|2); 0 = auto */
 } bsk_options;
 
 /*
@@ -176,19 +178,20 @@ double bsk_truncation_error(int N, double eps);
 
 /*
  * Launch-shape autotuner.  Times the candidate shapes (lanes per workgroup in
- * {256, 512, 1024} that fit the radius, output rows per workgroup in
- * {16 .. 256}) of the single-image forward for this exact request on the
+ * {256, 512, 1024} that fit the radius, the block's two pass sizes, output
+ * rows per workgroup in {16 .. 256}) of the single-image forward for this exact request on the
  * current device, using the caller's img and out buffers (out is overwritten
  * several times; the stream is synchronised), and caches the fastest.  Later
  * calls with the same clamped radius, folded-order count, H, W and precision,
- * and with opt->block == 0 and opt->strip_h == 0, use it.  `path` (nullable)
+ * and with opt->block, opt->strip_h and opt->order_chunk all 0, use it.  `path` (nullable)
  * names a JSON-lines cache file that is read first and rewritten with the
  * result; the environment variable BSK_TUNE_CACHE names a file read at first
- * use.  best_block, best_rows and best_ms (nullable) receive the winner.
+ * use.  best_block, best_rows, best_chunk and best_ms (nullable) receive the
+ * winner.
  */
 int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
                  const bsk_options *opt, const char *path, void *stream, int *best_block,
-                 int *best_rows, double *best_ms);
+                 int *best_rows, int *best_chunk, double *best_ms);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *bsk_last_error(void);

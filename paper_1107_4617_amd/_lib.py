@@ -37,7 +37,8 @@ EXPORTS = [
 class Options(ctypes.Structure):
     _fields_ = [("order_mode", ctypes.c_int), ("N", ctypes.c_int), ("precision", ctypes.c_int),
                 ("weight_eps", ctypes.c_double), ("kahan", ctypes.c_int), ("pitch_in", ctypes.c_int),
-                ("pitch_out", ctypes.c_int), ("block", ctypes.c_int), ("strip_h", ctypes.c_int)]
+                ("pitch_out", ctypes.c_int), ("block", ctypes.c_int), ("strip_h", ctypes.c_int),
+                ("order_chunk", ctypes.c_int)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -81,7 +82,7 @@ def load():
         "bsk_plan_info": (_i, [_i, _d, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
         "bsk_truncation_error": (_d, [_i, _d]),
         "bsk_autotune": (_i, [_vp, _i, _i, _i, _f, _f, _vp, ctypes.POINTER(Options), ctypes.c_char_p, _vp,
-                              ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+                              ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d)]),
         "bsk_last_error": (ctypes.c_char_p, []),
         "bsk_release": (_i, []),
         "bsk_version": (ctypes.c_char_p, []),

@@ -137,12 +137,13 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         return fail(BSK_EUNSUPPORTED, "clamped radius %d exceeds %d", r->rh, BSK_MAX_RADIUS);
 
     int block = o.block;
-    int tuned_S = 0;
-    if (o.block == 0 && o.strip_h == 0) {
-        int tb = 0, ts = 0;
-        if (tuned_shape(r->rh, r->plan.K, H, W, r->prec, &tb, &ts)) {
+    int tuned_S = 0, tuned_kc = 0;
+    if (o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
+        int tb = 0, ts = 0, tk = 0;
+        if (tuned_shape(r->rh, r->plan.K, H, W, r->prec, &tb, &ts, &tk)) {
             block = tb;
             tuned_S = ts;
+            tuned_kc = tk;
         }
     }
     if (block == 0) {
@@ -160,6 +161,17 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     if (block - 2 * r->rh < 1)
         return fail(BSK_EUNSUPPORTED, "radius %d too large for a %d-lane strip", r->rh, block);
     r->block = block;
+    if (o.order_chunk < 0) return fail(BSK_EINVAL, "order_chunk must be >= 0");
+    int kc = o.order_chunk ? o.order_chunk : tuned_kc;
+    if (kc == 0) {
+        // the half pass when it holds every order (or for small order counts),
+        // else the full pass
+        const int full = bsk::chunk_forward_f32(block);
+        kc = (r->plan.K <= full / 2) ? full / 2 : full;
+    }
+    if (!bsk::valid_chunk_forward_f32(block, kc))
+        return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
+    r->kc = kc;
     if (o.strip_h < 0) return fail(BSK_EINVAL, "strip_h must be >= 0");
     const int Wt = block - 2 * r->rh;
     const int strips = (W + Wt - 1) / Wt;
@@ -180,7 +192,7 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     return BSK_OK;
 }
 
-void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W)
+void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W, int kc)
 {
     std::memset(a, 0, sizeof(*a));
     a->io.H = H;
@@ -190,12 +202,16 @@ void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W)
     a->rh = r.rh;
     a->rv = r.rv;
     a->S = r.S;
-    a->K = r.plan.K;
+    a->K = (r.plan.K + kc - 1) / kc * kc;
     a->omega_base = r.plan.omega_base;
     a->delta = r.plan.delta;
+    a->start_mode = r.plan.start_mode;
     const int Wt = r.block - 2 * r.rh;
     a->strips = (W + Wt - 1) / Wt;
-    for (int m = 0; m < r.plan.K; ++m) a->v[m] = r.plan.v[m];
+    for (int m = 0; m < a->K; ++m) {
+        a->v[m] = m < r.plan.K ? r.plan.v[m] : 0.0;
+        a->vf[m] = (float)a->v[m];
+    }
 }
 
 int nblocks(const Resolved &r, int H, int W)
@@ -228,10 +244,10 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
     if (overlap(img, ((size_t)(H - 1) * r.pitch_in + W) * esz, out, ((size_t)(H - 1) * r.pitch_out + W) * esz))
         return fail(BSK_EINVAL, "img and out overlap");
     bsk::StripArgs a;
-    fill_args(&a, r, H, W);
+    const int kc = r.prec == BSK_FP64 ? bsk::chunk_forward_f64(r.block) : r.kc;
+    fill_args(&a, r, H, W, kc);
     a.io.img = img;
     a.io.out = out;
-    const int kc = r.prec == BSK_FP64 ? bsk::chunk_forward_f64(r.block) : bsk::chunk_forward_f32(r.block);
     if (r.plan.K > kc) {
         void *ws = nullptr;
         st = get_ws(stream, 0, (size_t)bsk::acc_count_forward() * H * W * esz, &ws);
@@ -240,7 +256,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
     }
     hipError_t e = r.prec == BSK_FP64
                        ? bsk::launch_forward_f64(a, r.block, (hipStream_t)stream)
-                       : bsk::launch_forward_f32(a, r.block, r.prec, r.kahan, (hipStream_t)stream);
+                       : bsk::launch_forward_f32(a, r.block, r.kc, r.prec, r.kahan, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return BSK_OK;
 }
@@ -248,7 +264,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
 int train_impl(const float *img, int H, int W, const Resolved &r, float *out, float *saved, void *stream)
 {
     bsk::StripArgs a;
-    fill_args(&a, r, H, W);
+    fill_args(&a, r, H, W, bsk::chunk_train_f32(r.block));
     a.io.img = img;
     a.io.out = out;
     a.io.out2 = saved;
@@ -326,7 +342,7 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
         saved = sv;
     }
     bsk::StripArgs a;
-    fill_args(&a, r, H, W);
+    fill_args(&a, r, H, W, bsk::chunk_backward_f32(r.block));
     a.io.img = img;
     a.io.aux0 = grad_out;
     a.io.aux1 = saved;                      // Q

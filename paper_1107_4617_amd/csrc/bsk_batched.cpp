@@ -21,6 +21,7 @@ namespace {
 struct BatchPlan {
     std::vector<bsk::BatchImage> imgs;
     std::vector<double> vtab;
+    std::vector<float> vtabf;
     long long ws_elems = 0;
     int total_units = 0;
     int block = 256;
@@ -74,6 +75,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         it.im.K = pl.K;
         it.im.omega_base = pl.omega_base;
         it.im.delta = pl.delta;
+        it.im.start_mode = pl.start_mode;
         it.v.assign(pl.v, pl.v + pl.K);
         max_rh = std::max(max_rh, it.im.rh);
         items.push_back(std::move(it));
@@ -103,6 +105,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     });
     bp->imgs.clear();
     bp->vtab.clear();
+    bp->vtabf.clear();
     bp->ws_elems = 0;
     long long units = 0;
     for (auto &it : items) {
@@ -110,7 +113,11 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         units += (long long)it.im.strips * ((it.im.H + it.im.S - 1) / it.im.S);
         if (units > (1LL << 30)) return fail(BSK_EINVAL, "too many work units");
         it.im.v_off = (int)bp->vtab.size();
+        // pad to whole passes with zero weights
+        it.im.K = (it.im.K + kc - 1) / kc * kc;
+        it.v.resize(it.im.K, 0.0);
         bp->vtab.insert(bp->vtab.end(), it.v.begin(), it.v.end());
+        for (double w : it.v) bp->vtabf.push_back((float)w);
         if (it.im.K > kc) {
             it.im.ws_off = bp->ws_elems;
             bp->ws_elems += (long long)bsk::acc_count_forward() * it.im.H * it.im.W;
@@ -132,29 +139,35 @@ struct DeviceBatch {
     bsk::BatchArgs args;
 };
 
-size_t table_bytes(const BatchPlan &bp, size_t *off_v, size_t *off_c)
+// Table layout: [images | FP64 weights | FP32 weights | counter], 256-byte aligned parts.
+size_t table_bytes(const BatchPlan &bp, size_t *off_v, size_t *off_f, size_t *off_c)
 {
     size_t a = bp.imgs.size() * sizeof(bsk::BatchImage);
     a = (a + 255) & ~(size_t)255;
     *off_v = a;
     a += bp.vtab.size() * sizeof(double);
     a = (a + 255) & ~(size_t)255;
+    *off_f = a;
+    a += bp.vtabf.size() * sizeof(float);
+    a = (a + 255) & ~(size_t)255;
     *off_c = a;
     return a + 256;
 }
 
-void pack_tables(const BatchPlan &bp, std::vector<char> *host, size_t *off_v, size_t *off_c)
+void pack_tables(const BatchPlan &bp, std::vector<char> *host, size_t *off_v, size_t *off_f, size_t *off_c)
 {
-    const size_t n = table_bytes(bp, off_v, off_c);
+    const size_t n = table_bytes(bp, off_v, off_f, off_c);
     host->assign(n, 0);
     std::memcpy(host->data(), bp.imgs.data(), bp.imgs.size() * sizeof(bsk::BatchImage));
     std::memcpy(host->data() + *off_v, bp.vtab.data(), bp.vtab.size() * sizeof(double));
+    std::memcpy(host->data() + *off_f, bp.vtabf.data(), bp.vtabf.size() * sizeof(float));
 }
 
-void set_args(DeviceBatch *db, const BatchPlan &bp, size_t off_v, size_t off_c)
+void set_args(DeviceBatch *db, const BatchPlan &bp, size_t off_v, size_t off_f, size_t off_c)
 {
     db->args.imgs = (const bsk::BatchImage *)db->tab;
     db->args.vtab = (const double *)((char *)db->tab + off_v);
+    db->args.vtabf = (const float *)((char *)db->tab + off_f);
     db->args.counter = (unsigned *)((char *)db->tab + off_c);
     db->args.ws = db->ws;
     db->args.nimg = (int)bp.imgs.size();
@@ -207,7 +220,7 @@ int stage_upload(void *stream, const std::vector<char> &tab, void *dev_dst)
 int grid_for(int block)
 {
     (void)block;
-    return device_cus();   // one resident workgroup per compute unit (LDS bound)
+    return 2 * device_cus();   // two resident workgroups per compute unit (LDS bound)
 }
 
 // ---------------------------------------------------------------- graphs --
@@ -260,7 +273,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int block, S;
+    int block, S, kc;
     double ms;
 };
 std::mutex g_tune_mu;
@@ -276,8 +289,8 @@ void load_tune_file(const char *path)
         TuneKey k;
         TuneVal v;
         if (std::sscanf(line, "{\"rh\": %d, \"K\": %d, \"H\": %d, \"W\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, "
-                              "\"ms\": %lf}",
-                        &k.rh, &k.K, &k.H, &k.W, &k.prec, &v.block, &v.S, &v.ms) == 8)
+                              "\"kc\": %d, \"ms\": %lf}",
+                        &k.rh, &k.K, &k.H, &k.W, &k.prec, &v.block, &v.S, &v.kc, &v.ms) == 9)
             g_tune[k] = v;
     }
     std::fclose(f);
@@ -290,9 +303,10 @@ void save_tune_file(const char *path)
     if (!f) return;
     for (auto &kv : g_tune)
         std::fprintf(f,
-                     "{\"rh\": %d, \"K\": %d, \"H\": %d, \"W\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, \"ms\": %.6f}\n",
+                     "{\"rh\": %d, \"K\": %d, \"H\": %d, \"W\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, "
+                     "\"kc\": %d, \"ms\": %.6f}\n",
                      kv.first.rh, kv.first.K, kv.first.H, kv.first.W, kv.first.prec, kv.second.block,
-                     kv.second.S, kv.second.ms);
+                     kv.second.S, kv.second.kc, kv.second.ms);
     std::fclose(f);
 }
 
@@ -301,7 +315,7 @@ void save_tune_file(const char *path)
 namespace bsk {
 namespace host {
 
-bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S)
+bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S, int *kc)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) {
@@ -312,6 +326,7 @@ bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S)
     if (it == g_tune.end()) return false;
     *block = it->second.block;
     *S = it->second.S;
+    *kc = it->second.kc;
     return true;
 }
 
@@ -325,9 +340,9 @@ int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T, con
     BatchPlan bp;
     int st = build_batch(descs, B, T, opt, &bp);
     if (st) return st;
-    size_t off_v, off_c;
+    size_t off_v, off_f, off_c;
     std::vector<char> host;
-    pack_tables(bp, &host, &off_v, &off_c);
+    pack_tables(bp, &host, &off_v, &off_f, &off_c);
     DeviceBatch db;
     st = get_ws(stream, 5, host.size(), &db.tab);
     if (st) return st;
@@ -337,7 +352,7 @@ int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T, con
         if (st) return st;
         db.ws = (float *)w;
     }
-    set_args(&db, bp, off_v, off_c);
+    set_args(&db, bp, off_v, off_f, off_c);
     st = stage_upload(stream, host, db.tab);
     if (st) return st;
     hipError_t e = bsk::launch_batched_f32(db.args, bp.block, grid_for(bp.block), (hipStream_t)stream);
@@ -367,9 +382,9 @@ int bilateral_shiftable_batched_graph(const bsk_image_desc *descs, int B, float 
     BatchPlan bp;
     int st = build_batch(descs, B, T, opt, &bp);
     if (st) return st;
-    size_t off_v, off_c;
+    size_t off_v, off_f, off_c;
     std::vector<char> host;
-    pack_tables(bp, &host, &off_v, &off_c);
+    pack_tables(bp, &host, &off_v, &off_f, &off_c);
     GraphEntry g;
     g.descs.assign(descs, descs + B);
     g.T = T;
@@ -398,7 +413,7 @@ int bilateral_shiftable_batched_graph(const bsk_image_desc *descs, int B, float 
     DeviceBatch db;
     db.tab = g.tab;
     db.ws = g.ws;
-    set_args(&db, bp, off_v, off_c);
+    set_args(&db, bp, off_v, off_f, off_c);
     e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         free_graph(g);
@@ -445,7 +460,7 @@ void bsk_release_batched(void)
 
 int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
                  const bsk_options *opt, const char *path, void *stream, int *best_block, int *best_rows,
-                 double *best_ms)
+                 int *best_chunk, double *best_ms)
 {
     if (!img || !out) return fail(BSK_EINVAL, "null pointer");
     bsk_options o;
@@ -453,6 +468,7 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     if (opt) o = *opt;
     o.block = 0;
     o.strip_h = 0;
+    o.order_chunk = 0;
     Resolved base;
     int st = resolve(H, W, radius, sigma_r, T, &o, &base);
     if (st) return st;
@@ -469,32 +485,39 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
         return fail(BSK_EHIP, "hipEventCreate failed");
     const int blocks[3] = {256, 512, 1024};
     const int rows[9] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
-    TuneVal best{0, 0, 1e30};
+    TuneVal best{0, 0, 0, 1e30};
     for (int b : blocks) {
         if (b - 2 * base.rh < b / 4 && !(b == 1024 && base.rh <= 511)) continue;
         if (b - 2 * base.rh < 1) continue;
-        for (int S : rows) {
-            if (S > H && S != rows[0]) continue;
-            bsk_options c = o;
-            c.block = b;
-            c.strip_h = S;
-            float ms_min = 1e30f;
-            for (int rep = 0; rep < 4; ++rep) {
-                if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) break;
-                st = bilateral_shiftable_ex(img, H, W, radius, sigma_r, T, out, &c, stream);
-                if (st) break;
-                if (hipEventRecord(e1, (hipStream_t)stream) != hipSuccess) break;
-                if (hipEventSynchronize(e1) != hipSuccess) break;
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
-                if (rep > 0 && ms < ms_min) ms_min = ms;   // first run is a warm-up
+        const int full = bsk::chunk_forward_f32(b);
+        const int kcs[2] = {full, full / 2};
+        for (int kc : kcs) {
+            // the FP64 forward has a single pass size
+            if (base.prec == BSK_FP64 && kc != full) continue;
+            for (int S : rows) {
+                if (S > H && S != rows[0]) continue;
+                bsk_options c = o;
+                c.block = b;
+                c.strip_h = S;
+                c.order_chunk = base.prec == BSK_FP64 ? 0 : kc;
+                float ms_min = 1e30f;
+                for (int rep = 0; rep < 4; ++rep) {
+                    if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) break;
+                    st = bilateral_shiftable_ex(img, H, W, radius, sigma_r, T, out, &c, stream);
+                    if (st) break;
+                    if (hipEventRecord(e1, (hipStream_t)stream) != hipSuccess) break;
+                    if (hipEventSynchronize(e1) != hipSuccess) break;
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (rep > 0 && ms < ms_min) ms_min = ms;   // first run is a warm-up
+                }
+                if (st) {
+                    hipEventDestroy(e0);
+                    hipEventDestroy(e1);
+                    return st;
+                }
+                if (ms_min < best.ms) best = TuneVal{b, S, c.order_chunk, (double)ms_min};
             }
-            if (st) {
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
-                return st;
-            }
-            if (ms_min < best.ms) best = TuneVal{b, S, (double)ms_min};
         }
     }
     hipEventDestroy(e0);
@@ -507,6 +530,7 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     }
     if (best_block) *best_block = best.block;
     if (best_rows) *best_rows = best.S;
+    if (best_chunk) *best_chunk = best.kc;
     if (best_ms) *best_ms = best.ms;
     return BSK_OK;
 }

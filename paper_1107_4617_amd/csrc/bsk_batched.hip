@@ -9,17 +9,20 @@
 
 namespace bsk {
 
+// Same pass shapes as the single-image FP32 forward (full pass).
 constexpr int kc_batched(int block) { return block == 256 ? 16 : block == 512 ? 8 : 4; }
+constexpr int kl_batched(int block) { return kc_batched(block) / 2; }
+
 int chunk_batched_f32(int block) { return kc_batched(block); }
 int max_radius_batched(int block) { return (block - 2) / 2; }
 
 __global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
 
 template <int BLOCK, int KC>
-__global__ void __launch_bounds__(BLOCK, 1) batched_kernel(const BatchArgs a)
+__global__ void __launch_bounds__(BLOCK, 2) batched_kernel(const BatchArgs a)
 {
-    constexpr int ROWS = PolForward<float>::NCH * KC;
-    __shared__ float lds[2 * ROWS * (BLOCK + 1)];
+    constexpr int ROWS = PolForward<float>::NCH * kl_batched(BLOCK);
+    __shared__ float lds[ROWS * (BLOCK + pow2_floor(BLOCK / ROWS))];
     __shared__ int unit_sh;
     for (;;) {
         if (threadIdx.x == 0) unit_sh = (int)atomicAdd(a.counter, 1u);
@@ -56,11 +59,15 @@ __global__ void __launch_bounds__(BLOCK, 1) batched_kernel(const BatchArgs a)
         gm.rv = im.rv;
         gm.S = im.S;
         gm.K = im.K;
+        gm.start_mode = im.start_mode;
         gm.omega_base = im.omega_base;
         gm.delta = im.delta;
         gm.v = a.vtab + im.v_off;
+        gm.vf = a.vtabf + im.v_off;
         gm.ws = im.ws_off >= 0 ? (void *)(a.ws + im.ws_off) : nullptr;
-        strip_body<float, BLOCK, KC, PolForward<float>, 0, false>(io, gm, bx, by, lds, nullptr, nullptr);
+        strip_body<float, BLOCK, KC, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
+                                                                                    nullptr, nullptr);
+        __syncthreads();
     }
 }
 

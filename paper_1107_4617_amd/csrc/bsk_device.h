@@ -14,22 +14,26 @@
 // segment of S output rows, which it walks from top to bottom.  Lane t owns
 // column j0 - rh + t.  Per output row i:
 //   phase V  every lane updates, in registers, the vertical moving sums of all
-//            channels of its column for the chunk's KC orders:
+//            channels of its column for the pass's KC orders:
 //            V += X(i + rv) - X(i - rv - 1).  The transforms X come from a
 //            rotation recurrence over the orders (one sincos pair per pixel,
 //            then a 2x2 rotation per order), so cos/sin are never evaluated
 //            per order.  V is written to an LDS row buffer.
-//   phase H  "walker" lanes, one per (order, channel, segment of columns),
-//            slide a horizontal window of width 2 rh + 1 along the LDS row:
-//            B(j) = B(j - 1) + V(j + rh) - V(j - rh - 1).
-//   phase R  every output lane recombines its pixel from the box sums of all
-//            orders and the transforms of its own value (kept in registers).
+//   phase H  "walker" lanes turn each LDS row into its prefix sums in place:
+//            each walker scans a chunk of the row in registers and the
+//            chunk totals are combined by a scan across the row's walkers.
+//   phase R  every output lane forms the horizontal box sums as prefix
+//            differences B(j) = P(j + rh) - P(j - rh - 1) and recombines its
+//            pixel from the box sums of all orders and the transforms of its
+//            own value (kept in registers).
 // The (channels x orders) stack therefore lives only in registers and LDS; HBM
 // sees the input (read ~3 times through L2: as incoming, centre and outgoing
-// row) and the output.  Values are centred on a per-workgroup reference level
-// before transforming (the filter is shift covariant), which halves the
-// magnitude of the f-weighted sums.  Orders beyond KC are processed in further
-// passes whose partial accumulators live in a workspace.
+// row, each load issued one row ahead) and the output.  Values are centred on
+// a per-workgroup reference level before transforming (the filter is shift
+// covariant), which halves the magnitude of the f-weighted sums.  The order
+// count is padded to a multiple of KC with zero weights, so every pass runs
+// the same straight-line code; passes after the first continue from partial
+// accumulators kept in a workspace.
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -41,7 +45,34 @@
 namespace bsk {
 
 // ------------------------------------------------------------------ helpers --
-__device__ __forceinline__ void sc(float x, float *s, float *c) { sincosf(x, s, c); }
+// sin and cos of a float angle: Cody-Waite reduction by pi/2 done in FP64
+// (exact enough for |x| up to ~1e6), then the Taylor polynomials of sin and cos
+// on [-pi/4, pi/4] (truncation error below 2e-9), and the quadrant rotation.
+// Branch-free, about twenty VALU instructions.
+__device__ __forceinline__ void fast_sincos(float x, float *s, float *c)
+{
+    const float k = rintf(x * 0.636619772367581343f);   // 2/pi
+    const float r = (float)__builtin_fma(-(double)k, 1.5707963267948966, (double)x);
+    const float r2 = r * r;
+    float ps = __builtin_fmaf(r2, 2.75573192239858907e-6f, -1.98412698412698413e-4f);
+    ps = __builtin_fmaf(r2, ps, 8.33333333333333333e-3f);
+    ps = __builtin_fmaf(r2, ps, -1.66666666666666667e-1f);
+    const float sr = __builtin_fmaf(r * r2, ps, r);
+    float pc = __builtin_fmaf(r2, -2.75573192239858907e-7f, 2.48015873015873016e-5f);
+    pc = __builtin_fmaf(r2, pc, -1.38888888888888889e-3f);
+    pc = __builtin_fmaf(r2, pc, 4.16666666666666667e-2f);
+    pc = __builtin_fmaf(r2, pc, -0.5f);
+    const float cr = __builtin_fmaf(r2, pc, 1.0f);
+    const int q = (int)k;
+    const float sv = (q & 1) ? cr : sr;
+    const float cv = (q & 1) ? sr : cr;
+    *s = (q & 2) ? -sv : sv;
+    *c = ((q + 1) & 2) ? -cv : cv;
+}
+__device__ __forceinline__ void sc(float x, float *s, float *c) { fast_sincos(x, s, c); }
+// fused multiply-add in the type of its arguments
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ void sc(double x, double *s, double *c) { sincos(x, s, c); }
 
 // Stack quantisation of the precision forms: 1 bfloat16, 2 float16 (both round
@@ -58,25 +89,46 @@ __device__ __forceinline__ float quant(float x)
 template <int QUANT>
 __device__ __forceinline__ double quant(double x) { return x; }
 
+// cos and sin of (omega_0 + m delta) g for m = 0, 1, ... by the three-term
+// recurrence x_{m+1} = 2 cos(delta g) x_m - x_{m-1}, which both sequences
+// satisfy (angle addition); one fused multiply-add per value and order.  The
+// start needs one sincos when omega_0 is 0 or delta / 2 (the first pass of an
+// even or odd order: the half-angle gives the step), two otherwise.  A pixel
+// outside the image starts at zero so all its channels vanish.
 template <typename AT>
 struct Chain {
-    AT c, s, cd, sd;
-    // (c, s) = (cos, sin)(om0 g), rotation step (cos, sin)(dlt g); a pixel
-    // outside the image starts at (0, 0) so all its channels vanish.
-    __device__ __forceinline__ void start(bool valid, AT g, AT om0, AT dlt)
+    AT c, s, cp, sp, a2;   // current, previous, 2 cos(delta g)
+    __device__ __forceinline__ void start(bool valid, AT g, AT om0, AT dlt, int mode)
     {
-        AT s0, c0, s1, c1;
-        sc(om0 * g, &s0, &c0);
-        sc(dlt * g, &s1, &c1);
-        c = valid ? c0 : AT(0);
-        s = valid ? s0 : AT(0);
-        cd = c1;
-        sd = s1;
+        AT c0, s0, cd, sd;
+        if (mode == 0) {            // omega_0 = 0
+            sc(dlt * g, &sd, &cd);
+            c0 = AT(1);
+            s0 = AT(0);
+        } else if (mode == 1) {     // omega_0 = delta / 2
+            AT sh, ch;
+            sc(om0 * g, &sh, &ch);
+            c0 = ch;
+            s0 = sh;
+            cd = AT(1) - AT(2) * sh * sh;
+            sd = AT(2) * sh * ch;
+        } else {
+            sc(om0 * g, &s0, &c0);
+            sc(dlt * g, &sd, &cd);
+        }
+        const AT z = valid ? AT(1) : AT(0);
+        c = z * c0;
+        s = z * s0;
+        cp = z * (c0 * cd + s0 * sd);   // (cos, sin) of (omega_0 - delta) g
+        sp = z * (s0 * cd - c0 * sd);
+        a2 = AT(2) * cd;
     }
     __device__ __forceinline__ void step()
     {
-        const AT cn = c * cd - s * sd;
-        const AT sn = s * cd + c * sd;
+        const AT cn = fmat(a2, c, -cp);
+        const AT sn = fmat(a2, s, -sp);
+        cp = c;
+        sp = s;
         c = cn;
         s = sn;
     }
@@ -86,22 +138,37 @@ template <typename T>
 __device__ __forceinline__ T ld(const void *p, long idx) { return ((const T *)p)[idx]; }
 
 // ------------------------------------------------------------------ policies --
-// A policy fixes the channels that are box-summed per order, the per-pixel
-// inputs they need, and how box sums recombine into per-pixel accumulators.
+// A policy fixes the channels that are box-summed per order, the raw per-pixel
+// inputs they need (fetched one row ahead), and how box sums recombine into
+// per-pixel accumulators.
+
+// Channels come in pairs (kappa_p C, kappa_p S) with a per-pixel coefficient
+// kappa_p; channel 2p is the cosine member and 2p+1 the sine member.
 
 // Forward: channels (C, S, gC, gS), g = f - ref; accumulators (Q, P).
 template <typename FT>
 struct PolForward {
-    static constexpr int NCH = 4, NACC = 2, NAUX = 1;
+    static constexpr int NCH = 4, NACC = 2, NAUX = 1, NRAW = 1, NPAIR = 2;
+    template <typename AT>
+    __device__ static void kappa(const AT *aux, AT *k)
+    {
+        k[0] = AT(1);
+        k[1] = aux[0];
+    }
     template <typename AT>
     __device__ static AT ref(const IO &a, int i, int j)
     {
         return (AT)ld<FT>(a.img, (long)i * a.pitch_in + j);
     }
     template <typename AT>
-    __device__ static void load(const IO &a, bool valid, int i, int j, AT ref, AT *aux)
+    __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
     {
-        aux[0] = valid ? (AT)ld<FT>(a.img, (long)i * a.pitch_in + j) - ref : AT(0);
+        raw[0] = valid ? (AT)ld<FT>(a.img, (long)i * a.pitch_in + j) : AT(0);
+    }
+    template <typename AT>
+    __device__ static void make(const AT *raw, AT ref, AT *aux)
+    {
+        aux[0] = raw[0] - ref;
     }
     template <typename AT>
     __device__ static void chans(AT C, AT S, const AT *aux, AT *X)
@@ -132,16 +199,28 @@ struct PolForward {
 // phi'(t) = -sum_m v_m omega_m sin(omega_m t).  Outputs u = ref + P/Q and the
 // planes Q, E1 = A1 - (u-ref) A0, E2 = A2 - (g_z + u - ref) A1 + g_z (u-ref) A0.
 struct PolTrain {
-    static constexpr int NCH = 6, NACC = 5, NAUX = 1;
+    static constexpr int NCH = 6, NACC = 5, NAUX = 1, NRAW = 1, NPAIR = 3;
+    template <typename AT>
+    __device__ static void kappa(const AT *aux, AT *k)
+    {
+        k[0] = AT(1);
+        k[1] = aux[0];
+        k[2] = aux[0] * aux[0];
+    }
     template <typename AT>
     __device__ static AT ref(const IO &a, int i, int j)
     {
         return (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
     }
     template <typename AT>
-    __device__ static void load(const IO &a, bool valid, int i, int j, AT ref, AT *aux)
+    __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
     {
-        aux[0] = valid ? (AT)ld<float>(a.img, (long)i * a.pitch_in + j) - ref : AT(0);
+        raw[0] = valid ? (AT)ld<float>(a.img, (long)i * a.pitch_in + j) : AT(0);
+    }
+    template <typename AT>
+    __device__ static void make(const AT *raw, AT ref, AT *aux)
+    {
+        aux[0] = raw[0] - ref;
     }
     template <typename AT>
     __device__ static void chans(AT C, AT S, const AT *aux, AT *X)
@@ -188,23 +267,38 @@ struct PolTrain {
 // and dL/df(z) = T1(z) - alpha(z) E1(z); per-workgroup partial sums of
 // alpha(x) E2(x) feed dL/dsigma_r.
 struct PolBackward {
-    static constexpr int NCH = 4, NACC = 1, NAUX = 3;
+    static constexpr int NCH = 4, NACC = 1, NAUX = 3, NRAW = 4, NPAIR = 2;
+    template <typename AT>
+    __device__ static void kappa(const AT *aux, AT *k)
+    {
+        k[0] = aux[1];
+        k[1] = aux[1] * aux[2];
+    }
     template <typename AT>
     __device__ static AT ref(const IO &a, int i, int j)
     {
         return (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
     }
     template <typename AT>
-    __device__ static void load(const IO &a, bool valid, int i, int j, AT ref, AT *aux)
+    __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
     {
         if (valid) {
             const long o = (long)i * a.W + j;
-            aux[0] = (AT)ld<float>(a.img, (long)i * a.pitch_in + j) - ref;
-            aux[1] = (AT)a.aux0[o] / (AT)a.aux1[o];
-            aux[2] = (AT)a.aux2[o] - ref;
+            raw[0] = (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
+            raw[1] = (AT)a.aux0[o];
+            raw[2] = (AT)a.aux1[o];
+            raw[3] = (AT)a.aux2[o];
         } else {
-            aux[0] = aux[1] = aux[2] = AT(0);
+            raw[0] = raw[1] = raw[3] = AT(0);
+            raw[2] = AT(1);
         }
+    }
+    template <typename AT>
+    __device__ static void make(const AT *raw, AT ref, AT *aux)
+    {
+        aux[0] = raw[0] - ref;
+        aux[1] = raw[1] / raw[2];
+        aux[2] = raw[3] - ref;
     }
     template <typename AT>
     __device__ static void chans(AT C, AT S, const AT *aux, AT *X)
@@ -234,25 +328,48 @@ struct PolBackward {
 
 // ---------------------------------------------------------------- the body --
 struct Geom {
-    int H, W, pitch_in, pitch_out, rh, rv, S, K;
+    int H, W, pitch_in, pitch_out, rh, rv, S, K;   // K: padded to a multiple of KC
+    int start_mode;    // first pass: 0 omega_0 = 0, 1 omega_0 = delta / 2, 2 general
     double omega_base, delta;
-    const double *v;  // folded weights, K entries
-    void *ws;         // NACC planes of H*W accumulators, or null when K <= KC
+    const double *v;   // folded weights (FP64), K entries, zero past the kept orders
+    const float *vf;   // the same weights in FP32
+    void *ws;          // NACC planes of H*W accumulators, or null when K <= KC
 };
 
-template <typename AT, int BLOCK, int KC, class POL, int QUANT, bool KAHAN>
+template <typename AT>
+__device__ __forceinline__ AT weight(const Geom &gm, int m);
+template <>
+__device__ __forceinline__ float weight<float>(const Geom &gm, int m) { return gm.vf[m]; }
+template <>
+__device__ __forceinline__ double weight<double>(const Geom &gm, int m) { return gm.v[m]; }
+
+// Walker geometry of one LDS row of BLOCK columns: CH walkers (a power of two,
+// at most one wavefront) per row, each owning G consecutive columns.  Column
+// col lives at col + col / G, so the row stride is BLOCK + CH; with CH walkers
+// per row and 64 / CH rows per wavefront the walkers' simultaneous accesses
+// fall on distinct banks.
+constexpr int pow2_floor(int x) { return x >= 64 ? 64 : x >= 32 ? 32 : x >= 16 ? 16 : x >= 8 ? 8 : x >= 4 ? 4 : x >= 2 ? 2 : 1; }
+
+// KR orders are carried in registers per pass (the vertical sums of all their
+// channels); they go through LDS KL orders at a time (NCH * KL rows).
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
 __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, int by, AT *lds,
                                            double *red_lds, double *red_out)
 {
     constexpr int NCH = POL::NCH;
     constexpr int NACC = POL::NACC;
     constexpr int NAUX = POL::NAUX;
-    constexpr int ROWS = NCH * KC;
-    constexpr int STRIDE = BLOCK + 1;
-    constexpr int NSEG = BLOCK / ROWS;
-    static_assert(NSEG >= 1, "too many walker rows for the block");
+    constexpr int NRAW = POL::NRAW;
+    constexpr int NPAIR = POL::NPAIR;
+    constexpr int ROWS = NCH * KL;
+    constexpr int CH = pow2_floor(BLOCK / ROWS);
+    constexpr int G = BLOCK / CH;
+    constexpr int RS = BLOCK + CH;
+    constexpr int NSUB = KR / KL;
+    static_assert(NCH == 2 * NPAIR, "channels come in (cos, sin) pairs");
+    static_assert(KR % KL == 0, "KR must be a multiple of KL");
+    static_assert(CH * G == BLOCK && ROWS * CH <= BLOCK, "walker geometry");
     AT *Vb = lds;
-    AT *Bb = lds + ROWS * STRIDE;
 
     const int t = threadIdx.x;
     const int H = gm.H, W = gm.W, rh = gm.rh, rv = gm.rv;
@@ -268,28 +385,34 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     const AT ref = POL::template ref<AT>(a, i0, min(W - 1, j0 + Wt / 2));
     const long plane = (long)H * W;
 
-    // walker assignment (fixed for the whole launch)
-    const int wseg = t / ROWS;
-    const int wrow = t - wseg * ROWS;
-    const int wm = wrow / NCH;
-    const int L = (Wt + NSEG - 1) / NSEG;
-    const int jlim = min(rh + Wt, rh + (W - j0));   // lane index bound of useful outputs
-    const int js = rh + wseg * L;
-    const int je = min(jlim, js + L);
+    // LDS positions: this lane's column (phase V), its walker chunk (phase H),
+    // and the two prefix positions its output needs (phase R)
+    const int vpos = t + t / G;
+    const int wrow = t / CH;
+    const int wch = t - wrow * CH;
+    const bool walker = wrow < ROWS;
+    const int wbase = wrow * RS + wch * (G + 1);
+    // P(-1) = 0 is read from a pad slot (position G of the row: never written
+    // by phase V or the walkers, zeroed below)
+    const int phi = (t + rh) + (t + rh) / G;
+    const int plo_col = t - rh - 1;
+    const int plo = plo_col >= 0 ? plo_col + plo_col / G : G;
+    if (walker) Vb[wrow * RS + wch * (G + 1) + G] = AT(0);
+    __syncthreads();
 
     double red = 0.0;
 
-    for (int m0 = 0; m0 < gm.K; m0 += KC) {
-        const int kc = min(KC, gm.K - m0);
+    for (int m0 = 0; m0 < gm.K; m0 += KR) {
         const bool first = (m0 == 0);
-        const bool last = (m0 + KC >= gm.K);
+        const bool last = (m0 + KR >= gm.K);
         const AT om0 = (AT)(gm.omega_base + (double)m0 * gm.delta);
         const AT dlt = (AT)gm.delta;
+        const int smode = first ? gm.start_mode : 2;
 
-        AT V[KC][NCH];
-        AT Cmp[KAHAN ? KC : 1][NCH];
+        AT V[KR][NCH];
+        AT Cmp[KAHAN ? KR : 1][NCH];
 #pragma unroll
-        for (int m = 0; m < KC; ++m)
+        for (int m = 0; m < KR; ++m)
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 V[m][ch] = AT(0);
@@ -297,96 +420,146 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
             }
 
         // initial window: rows [i0 - rv, i0 + rv - 1] (the first step adds i0 + rv)
-        for (int y = ylo; y < yhi; ++y) {
-            AT aux[NAUX];
-            POL::template load<AT>(a, colok, y, jx, ref, aux);
-            Chain<AT> ch;
-            ch.start(colok, aux[0], om0, dlt);
+        {
+            AT raw[NRAW];
+            if (ylo < yhi) POL::template fetch<AT>(a, colok, ylo, jx, raw);
+            for (int y = ylo; y < yhi; ++y) {
+                AT aux[NAUX], kp[NPAIR];
+                POL::template make<AT>(raw, ref, aux);
+                POL::template kappa<AT>(aux, kp);
+                if (y + 1 < yhi) POL::template fetch<AT>(a, colok, y + 1, jx, raw);
+                Chain<AT> ch;
+                ch.start(colok, aux[0], om0, dlt, smode);
 #pragma unroll
-            for (int m = 0; m < KC; ++m) {
-                if (m < kc) {
-                    AT X[NCH];
-                    POL::template chans<AT>(quant<QUANT>(ch.c), quant<QUANT>(ch.s), aux, X);
+                for (int m = 0; m < KR; ++m) {
+                    const AT C = quant<QUANT>(ch.c), S = quant<QUANT>(ch.s);
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) V[m][c] += X[c];
+                    for (int p = 0; p < NPAIR; ++p) {
+                        V[m][2 * p] = fmat(kp[p], C, V[m][2 * p]);
+                        V[m][2 * p + 1] = fmat(kp[p], S, V[m][2 * p + 1]);
+                    }
                     ch.step();
                 }
             }
+        }
+
+        // raw inputs of the next row, fetched one row ahead
+        AT rin[NRAW], rout[NRAW], rc[NRAW];
+        {
+            const int yin = i0 + rv, yout = i0 - rv - 1;
+            POL::template fetch<AT>(a, colok && yin < H, yin, jx, rin);
+            POL::template fetch<AT>(a, colok && yout >= ylo, yout, jx, rout);
+            POL::template fetch<AT>(a, colok, i0, jx, rc);
         }
 
         for (int i = i0; i < i1; ++i) {
             const int yin = i + rv, yout = i - rv - 1;
             const bool vin = colok && (yin < H);
             const bool vout = colok && (yout >= ylo);
-            AT auxi[NAUX], auxo[NAUX], auxc[NAUX];
-            POL::template load<AT>(a, vin, yin, jx, ref, auxi);
-            POL::template load<AT>(a, vout, yout, jx, ref, auxo);
-            POL::template load<AT>(a, colok, i, jx, ref, auxc);
+            AT auxi[NAUX], auxo[NAUX], auxc[NAUX], ki[NPAIR], ko[NPAIR];
+            POL::template make<AT>(rin, ref, auxi);
+            POL::template make<AT>(rout, ref, auxo);
+            POL::template make<AT>(rc, ref, auxc);
+            POL::template kappa<AT>(auxi, ki);
+            POL::template kappa<AT>(auxo, ko);
+            if (i + 1 < i1) {
+                POL::template fetch<AT>(a, colok && yin + 1 < H, yin + 1, jx, rin);
+                POL::template fetch<AT>(a, colok && yout + 1 >= ylo, yout + 1, jx, rout);
+                POL::template fetch<AT>(a, colok, i + 1, jx, rc);
+            }
             Chain<AT> ci, co, cc;
-            ci.start(vin, auxi[0], om0, dlt);
-            co.start(vout, auxo[0], om0, dlt);
-            cc.start(colok, auxc[0], om0, dlt);
-            AT Cc[KC], Sc[KC];
+            ci.start(vin, auxi[0], om0, dlt, smode);
+            co.start(vout, auxo[0], om0, dlt, smode);
+            cc.start(colok, auxc[0], om0, dlt, smode);
+            AT acc[NACC];
+#pragma unroll
+            for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
 
-            // ---- phase V: vertical moving sums, transforms by rotation
 #pragma unroll
-            for (int m = 0; m < KC; ++m) {
-                if (m < kc) {
-                    AT Xi[NCH], Xo[NCH];
-                    POL::template chans<AT>(quant<QUANT>(ci.c), quant<QUANT>(ci.s), auxi, Xi);
-                    POL::template chans<AT>(quant<QUANT>(co.c), quant<QUANT>(co.s), auxo, Xo);
+            for (int h = 0; h < NSUB; ++h) {
+                AT Cc[KL], Sc[KL];
+                // ---- phase V: vertical moving sums V += X(in) - X(out), transforms by rotation
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
+                for (int k = 0; k < KL; ++k) {
+                    const int m = h * KL + k;
+                    const AT Ci = quant<QUANT>(ci.c), Si = quant<QUANT>(ci.s);
+                    const AT Co = quant<QUANT>(co.c), So = quant<QUANT>(co.s);
+#pragma unroll
+                    for (int p = 0; p < NPAIR; ++p) {
                         if constexpr (KAHAN) {
-                            const AT y = (Xi[c] - Xo[c]) - Cmp[m][c];
-                            const AT s = V[m][c] + y;
-                            Cmp[m][c] = (s - V[m][c]) - y;
-                            V[m][c] = s;
+                            const AT x[2] = {ki[p] * Ci - ko[p] * Co, ki[p] * Si - ko[p] * So};
+#pragma unroll
+                            for (int e = 0; e < 2; ++e) {
+                                const int c = 2 * p + e;
+                                const AT y = x[e] - Cmp[m][c];
+                                const AT s = V[m][c] + y;
+                                Cmp[m][c] = (s - V[m][c]) - y;
+                                V[m][c] = s;
+                            }
                         } else {
-                            V[m][c] += Xi[c] - Xo[c];
+                            V[m][2 * p] = fmat(-ko[p], Co, fmat(ki[p], Ci, V[m][2 * p]));
+                            V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
                         }
-                        Vb[(m * NCH + c) * STRIDE + t] = V[m][c];
                     }
-                    Cc[m] = quant<QUANT>(cc.c);
-                    Sc[m] = quant<QUANT>(cc.s);
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) Vb[(k * NCH + c) * RS + vpos] = V[m][c];
+                    Cc[k] = quant<QUANT>(cc.c);
+                    Sc[k] = quant<QUANT>(cc.s);
                     ci.step();
                     co.step();
                     cc.step();
                 }
-            }
-            __syncthreads();
+                __syncthreads();
 
-            // ---- phase H: horizontal moving sums by sliding walkers
-            if (wseg < NSEG && wm < kc && js < je) {
-                const AT *vr = Vb + wrow * STRIDE;
-                AT *br = Bb + wrow * STRIDE;
-                AT acc = AT(0);
-                for (int q = js - rh; q <= js + rh; ++q) acc += vr[q];
-                br[js] = acc;
-                for (int j = js + 1; j < je; ++j) {
-                    acc += vr[j + rh] - vr[j - rh - 1];
-                    br[j] = acc;
-                }
-            }
-            __syncthreads();
-
-            // ---- phase R: recombination with the shift identity
-            if (outlane) {
-                AT acc[NACC];
+                // ---- phase H: each row's prefix sums, computed in place by CH walkers
+                {
+                    AT loc[G];
+                    AT run = AT(0);
+                    if (walker) {
 #pragma unroll
-                for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
+                        for (int u = 0; u < G; ++u) loc[u] = Vb[wbase + u];
 #pragma unroll
-                for (int m = 0; m < KC; ++m) {
-                    if (m < kc) {
-                        AT B[NCH];
+                        for (int u = 0; u < G; ++u) {
+                            run += loc[u];
+                            loc[u] = run;
+                        }
+                    }
+                    // exclusive scan of the chunk totals over the row's CH lanes
+                    AT inc = run;
 #pragma unroll
-                        for (int c = 0; c < NCH; ++c) B[c] = Bb[(m * NCH + c) * STRIDE + t];
-                        const double om = gm.omega_base + (double)(m0 + m) * gm.delta;
-                        const AT v = (AT)gm.v[m0 + m];
-                        const AT vom = (AT)(gm.v[m0 + m] * om);
-                        POL::template recombine<AT>(v, vom, Cc[m], Sc[m], B, auxc, acc);
+                    for (int d = 1; d < CH; d <<= 1) {
+                        const AT y = __shfl_up(inc, d, CH);
+                        if (wch >= d) inc += y;
+                    }
+                    const AT off = inc - run;
+                    if (walker) {
+#pragma unroll
+                        for (int u = 0; u < G; ++u) Vb[wbase + u] = loc[u] + off;
                     }
                 }
+                __syncthreads();
+
+                // ---- phase R: box sums as prefix differences, recombined with the shift identity
+                if (outlane) {
+#pragma unroll
+                    for (int k = 0; k < KL; ++k) {
+                        const int m = h * KL + k;
+                        AT B[NCH];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            const AT *row = Vb + (k * NCH + c) * RS;
+                            B[c] = row[phi] - row[plo];
+                        }
+                        const AT v = weight<AT>(gm, m0 + m);
+                        const AT vom = v * (om0 + (AT)m * dlt);
+                        POL::template recombine<AT>(v, vom, Cc[k], Sc[k], B, auxc, acc);
+                    }
+                }
+                // the next sub-phase overwrites the rows read above
+                if (NSUB > 1 && h + 1 < NSUB) __syncthreads();
+            }
+
+            if (outlane) {
                 const long o = (long)i * W + jx;
                 if (!first) {
 #pragma unroll
@@ -399,6 +572,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     for (int q = 0; q < NACC; ++q) ((AT *)gm.ws)[q * plane + o] = acc[q];
                 }
             }
+            // the next row's phase V overwrites the rows phase R just read
+            __syncthreads();
         }
     }
 

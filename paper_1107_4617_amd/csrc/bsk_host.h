@@ -22,18 +22,21 @@ struct Resolved {
     int pitch_in, pitch_out;
     int rh, rv;
     int block;
+    int kc;        // FP32 forward orders per pass (other kernels use their own)
     int S;
     bsk::Plan plan;
 };
 
 int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r);
-void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W);
+// Fills the launch arguments; the weights are padded with zeros to a multiple
+// of `kc` (the pass size of the kernel that will run).
+void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W, int kc);
 int nblocks(const Resolved &r, int H, int W);
 bool overlap(const void *a, size_t na, const void *b, size_t nb);
 
 // Tuned launch shape for a single-image forward request, if the autotuner has
 // measured one for this (radius, orders, H, W, precision); returns false if not.
-bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S);
+bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S, int *kc);
 
 }  // namespace host
 }  // namespace bsk

@@ -6,7 +6,8 @@
 
 namespace bsk {
 
-constexpr int kMaxOrders = 256;   // folded orders carried in kernel arguments
+constexpr int kMaxOrders = 256;   // folded orders a plan may keep
+constexpr int kArgOrders = 272;   // weight slots in kernel arguments (kept orders padded to a pass)
 
 // Folded plan of the raised-cosine range kernel (Section 3, q_N, eq. (6)).
 // The unfolded expansion cos^N(a) = 2^-N sum_n C(N,n) cos((2n-N) a) pairs
@@ -23,6 +24,7 @@ struct Plan {
     double omega_base = 0.0; // omega(0)
     double delta = 0.0;      // omega(m+1) - omega(m)
     double dropped = 0.0;    // unfolded weight mass removed by truncation
+    int start_mode = 0;      // first pass chain start: 0 omega(0) = 0 (even N, N = 0), 1 omega(0) = delta / 2 (odd N)
     double v[kMaxOrders];    // folded weights (FP64)
 };
 
@@ -55,20 +57,25 @@ struct StripArgs {
     int rh, rv;            // clamped horizontal / vertical radii
     int S;                 // output rows per workgroup
     int K;                 // folded orders
+    int start_mode;        // 0: omega(0) = 0, 1: omega(0) = delta / 2, 2: general
     int strips;            // workgroups across the width
     double omega_base, delta;
-    double v[kMaxOrders];
+    double v[kArgOrders];  // folded weights, zero past the kept orders
+    float vf[kArgOrders];  // the same in FP32
 };
 
 // Launch helpers implemented in bsk_kernels.hip.  `prec` selects the stack
 // quantisation (bsk_precision) for the FP32 kernels.
-hipError_t launch_forward_f32(const StripArgs &a, int block, int prec, int kahan, hipStream_t s);
+hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s);
 hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s);
 hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s);
 hipError_t launch_backward_f32(const StripArgs &a, int block, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s);
 
-// Orders per chunk (one pass of the strip kernel) for a kernel family/block.
+// Orders per pass of the strip kernel for a kernel family/block; the FP32
+// forward offers two pass sizes per block (the smaller one halves the LDS
+// footprint, letting two workgroups share a compute unit).
+bool valid_chunk_forward_f32(int block, int kc);
 int chunk_forward_f32(int block);
 int chunk_forward_f64(int block);
 int chunk_train_f32(int block);
@@ -82,6 +89,7 @@ struct BatchImage {
     const float *img;
     float *out;
     int H, W, rh, rv, S, K;
+    int start_mode;          // as in StripArgs
     int strips;
     int unit0;               // first work unit of this image
     long long ws_off;        // offset of this image's accumulator planes in ws, -1 if none
@@ -91,7 +99,8 @@ struct BatchImage {
 
 struct BatchArgs {
     const BatchImage *imgs;  // device table, ordered by unit0
-    const double *vtab;      // device folded weights
+    const double *vtab;      // device folded weights (each image padded to a pass)
+    const float *vtabf;      // the same in FP32
     float *ws;               // partial accumulators for images with K > chunk
     int nimg;
     int total_units;

@@ -5,11 +5,30 @@
 
 namespace bsk {
 
-template <typename AT, int BLOCK, int KC, class POL, int QUANT, bool KAHAN>
-__global__ void __launch_bounds__(BLOCK, 1) strip_kernel(const StripArgs a)
+// Workgroups per compute unit that the LDS row buffers allow (160 KiB per CU).
+constexpr int lds_occupancy(int bytes) { return bytes <= 80 * 1024 ? 2 : 1; }
+
+// Pass shapes per lane count: orders in registers (full pass KR, half pass)
+// and orders per LDS sub-phase KL.  The LDS row buffer (NCH * KL rows of
+// BLOCK + CH elements) stays under 80 KiB, so at least two workgroups share a
+// compute unit.
+constexpr int kr_f32(int block) { return block == 256 ? 16 : block == 512 ? 8 : 4; }
+constexpr int kl_f32(int block) { return kr_f32(block) / 2; }
+constexpr int kr_f64(int block) { return block == 256 ? 8 : block == 512 ? 4 : 1; }
+constexpr int kl_f64(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
+// the adjoint keeps fewer orders in registers (its policy needs more of them)
+constexpr int kr_bwd(int block) { return block == 256 ? 8 : block == 512 ? 8 : 2; }
+constexpr int kl_bwd(int block) { return block == 256 ? 8 : block == 512 ? 4 : 2; }
+constexpr int kr_train(int block) { return block == 256 ? 10 : block == 512 ? 6 : 2; }
+constexpr int kl_train(int block) { return kr_train(block) / 2; }
+template <int NCH, int KL, int BLOCK, typename AT>
+constexpr int lds_elems() { return NCH * KL * (BLOCK + pow2_floor(BLOCK / (NCH * KL))); }
+
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
+__global__ void __launch_bounds__(BLOCK, lds_occupancy(lds_elems<POL::NCH, KL, BLOCK, AT>() * (int)sizeof(AT)))
+    strip_kernel(const StripArgs a)
 {
-    constexpr int ROWS = POL::NCH * KC;
-    __shared__ AT lds[2 * ROWS * (BLOCK + 1)];
+    __shared__ AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
     Geom gm;
     gm.H = a.io.H;
     gm.W = a.io.W;
@@ -19,18 +38,20 @@ __global__ void __launch_bounds__(BLOCK, 1) strip_kernel(const StripArgs a)
     gm.rv = a.rv;
     gm.S = a.S;
     gm.K = a.K;
+    gm.start_mode = a.start_mode;
     gm.omega_base = a.omega_base;
     gm.delta = a.delta;
     gm.v = a.v;
+    gm.vf = a.vf;
     gm.ws = a.ws;
-    strip_body<AT, BLOCK, KC, POL, QUANT, KAHAN>(a.io, gm, blockIdx.x, blockIdx.y, lds, nullptr, nullptr);
+    strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, blockIdx.x, blockIdx.y, lds, nullptr, nullptr);
 }
 
-template <int BLOCK, int KC>
-__global__ void __launch_bounds__(BLOCK, 1) backward_kernel(const StripArgs a)
+template <int BLOCK, int KR, int KL>
+__global__ void __launch_bounds__(BLOCK, lds_occupancy(lds_elems<PolBackward::NCH, KL, BLOCK, float>() * 4))
+    backward_kernel(const StripArgs a)
 {
-    constexpr int ROWS = PolBackward::NCH * KC;
-    __shared__ float lds[2 * ROWS * (BLOCK + 1)];
+    __shared__ float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
     __shared__ double red_lds[BLOCK];
     Geom gm;
     gm.H = a.io.H;
@@ -41,12 +62,14 @@ __global__ void __launch_bounds__(BLOCK, 1) backward_kernel(const StripArgs a)
     gm.rv = a.rv;
     gm.S = a.S;
     gm.K = a.K;
+    gm.start_mode = a.start_mode;
     gm.omega_base = a.omega_base;
     gm.delta = a.delta;
     gm.v = a.v;
+    gm.vf = a.vf;
     gm.ws = a.ws;
-    strip_body<float, BLOCK, KC, PolBackward, 0, false>(a.io, gm, blockIdx.x, blockIdx.y, lds, red_lds,
-                                                         a.red + (blockIdx.y * gridDim.x + blockIdx.x));
+    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(
+        a.io, gm, blockIdx.x, blockIdx.y, lds, red_lds, a.red + (blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // Fixed-order sum of the per-workgroup partials: grad_sigma = -(1/sigma) sum.
@@ -66,55 +89,62 @@ __global__ void __launch_bounds__(256) sigma_reduce_kernel(const float *unused, 
 }
 
 // ---------------------------------------------------------------- launches --
-template <typename AT, int BLOCK, int KC, class POL, int QUANT, bool KAHAN>
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
 static hipError_t launch(const StripArgs &a, hipStream_t s)
 {
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
-    hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KC, POL, QUANT, KAHAN>), grid, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-// Orders per pass: the two LDS row buffers hold 2 * NCH * KC * (BLOCK + 1)
-// elements, kept near 128 KiB of the 160 KiB per compute unit.
-constexpr int kc_f32_fwd(int block) { return block == 256 ? 16 : block == 512 ? 8 : 4; }
-constexpr int kc_f64_fwd(int block) { return block == 256 ? 8 : block == 512 ? 4 : 2; }
-constexpr int kc_f32_train(int block) { return block == 256 ? 10 : block == 512 ? 5 : 2; }
-
-int chunk_forward_f32(int block) { return kc_f32_fwd(block); }
-int chunk_forward_f64(int block) { return kc_f64_fwd(block); }
-int chunk_train_f32(int block) { return kc_f32_train(block); }
-int chunk_backward_f32(int block) { return kc_f32_fwd(block); }
+bool valid_chunk_forward_f32(int block, int kc)
+{
+    return kc == kr_f32(block) || kc == kl_f32(block);
+}
+int chunk_forward_f32(int block) { return kr_f32(block); }
+int chunk_forward_f64(int block) { return kr_f64(block); }
+int chunk_train_f32(int block) { return kr_train(block); }
+int chunk_backward_f32(int block) { return kr_bwd(block); }
 int acc_count_forward() { return PolForward<float>::NACC; }
 int acc_count_train() { return PolTrain::NACC; }
 int acc_count_backward() { return PolBackward::NACC; }
 
+template <int BLOCK, int QUANT, bool KAHAN>
+static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s)
+{
+    constexpr int KR = kr_f32(BLOCK), KL = kl_f32(BLOCK);
+    if (kc == KR) return launch<float, BLOCK, KR, KL, PolForward<float>, QUANT, KAHAN>(a, s);
+    return launch<float, BLOCK, KL, KL, PolForward<float>, QUANT, KAHAN>(a, s);
+}
+
 template <int QUANT, bool KAHAN>
-static hipError_t fwd32(const StripArgs &a, int block, hipStream_t s)
+static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s)
 {
     switch (block) {
-    case 256: return launch<float, 256, kc_f32_fwd(256), PolForward<float>, QUANT, KAHAN>(a, s);
-    case 512: return launch<float, 512, kc_f32_fwd(512), PolForward<float>, QUANT, KAHAN>(a, s);
-    case 1024: return launch<float, 1024, kc_f32_fwd(1024), PolForward<float>, QUANT, KAHAN>(a, s);
+    case 256: return fwd32_block<256, QUANT, KAHAN>(a, kc, s);
+    case 512: return fwd32_block<512, QUANT, KAHAN>(a, kc, s);
+    case 1024: return fwd32_block<1024, QUANT, KAHAN>(a, kc, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_forward_f32(const StripArgs &a, int block, int prec, int kahan, hipStream_t s)
+hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s)
 {
-    if (prec == 1) return kahan ? fwd32<1, true>(a, block, s) : fwd32<1, false>(a, block, s);
-    if (prec == 2) return kahan ? fwd32<2, true>(a, block, s) : fwd32<2, false>(a, block, s);
-    if (prec == 4) return kahan ? fwd32<4, true>(a, block, s) : fwd32<4, false>(a, block, s);
-    return kahan ? fwd32<0, true>(a, block, s) : fwd32<0, false>(a, block, s);
+    if (!valid_chunk_forward_f32(block, kc)) return hipErrorInvalidValue;
+    if (prec == 1) return kahan ? fwd32<1, true>(a, block, kc, s) : fwd32<1, false>(a, block, kc, s);
+    if (prec == 2) return kahan ? fwd32<2, true>(a, block, kc, s) : fwd32<2, false>(a, block, kc, s);
+    if (prec == 4) return kahan ? fwd32<4, true>(a, block, kc, s) : fwd32<4, false>(a, block, kc, s);
+    return kahan ? fwd32<0, true>(a, block, kc, s) : fwd32<0, false>(a, block, kc, s);
 }
 
 hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s)
 {
     switch (block) {
-    case 256: return launch<double, 256, kc_f64_fwd(256), PolForward<double>, 0, false>(a, s);
-    case 512: return launch<double, 512, kc_f64_fwd(512), PolForward<double>, 0, false>(a, s);
-    case 1024: return launch<double, 1024, kc_f64_fwd(1024), PolForward<double>, 0, false>(a, s);
+    case 256: return launch<double, 256, kr_f64(256), kl_f64(256), PolForward<double>, 0, false>(a, s);
+    case 512: return launch<double, 512, kr_f64(512), kl_f64(512), PolForward<double>, 0, false>(a, s);
+    case 1024: return launch<double, 1024, kr_f64(1024), kl_f64(1024), PolForward<double>, 0, false>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -122,9 +152,9 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s)
 hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s)
 {
     switch (block) {
-    case 256: return launch<float, 256, kc_f32_train(256), PolTrain, 0, false>(a, s);
-    case 512: return launch<float, 512, kc_f32_train(512), PolTrain, 0, false>(a, s);
-    case 1024: return launch<float, 1024, kc_f32_train(1024), PolTrain, 0, false>(a, s);
+    case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false>(a, s);
+    case 512: return launch<float, 512, kr_train(512), kl_train(512), PolTrain, 0, false>(a, s);
+    case 1024: return launch<float, 1024, kr_train(1024), kl_train(1024), PolTrain, 0, false>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -135,7 +165,7 @@ static hipError_t bwd(const StripArgs &a, hipStream_t s)
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
-    hipLaunchKernelGGL((backward_kernel<BLOCK, kc_f32_fwd(BLOCK)>), grid, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((backward_kernel<BLOCK, kr_bwd(BLOCK), kl_bwd(BLOCK)>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

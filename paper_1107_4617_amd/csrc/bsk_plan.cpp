@@ -70,6 +70,7 @@ int make_plan(int N, double sigma_r, double eps, Plan *p)
         p->omega_base = 0.0;
         p->delta = 0.0;
         p->v[0] = 1.0;
+        p->start_mode = 0;
         return 0;
     }
     const double s = p->gamma / std::sqrt((double)N);   // frequency unit
@@ -81,6 +82,7 @@ int make_plan(int N, double sigma_r, double eps, Plan *p)
     //   N odd:  (2m + 1) s.
     p->omega_base = (N & 1) ? s : 0.0;
     p->delta = 2.0 * s;
+    p->start_mode = (N & 1) ? 1 : 0;
     double w = central_weight(N);
     int k = 0;
     bool stop = false;

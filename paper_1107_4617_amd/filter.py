@@ -35,7 +35,7 @@ def _check_image(t: torch.Tensor, name: str, dtype=torch.float32):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, strip_h=0):
+def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, strip_h=0, order_chunk=0):
     o = _lib.Options()
     if N is None:
         o.order_mode = 0
@@ -48,6 +48,7 @@ def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, str
     o.kahan = 1 if kahan else 0
     o.block = int(block)
     o.strip_h = int(strip_h)
+    o.order_chunk = int(order_chunk)
     return o
 
 
@@ -69,12 +70,13 @@ def plan_info(N: int, eps: float = 0.0):
 
 def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,
               precision: str = "fp32", weight_eps: float = 0.0, kahan: bool = False, block: int = 0,
-              strip_h: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+              strip_h: int = 0, order_chunk: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Bilateral filter with a (2r+1)^2 box window and the range kernel cos^N(t / (sigma_r sqrt N)).
 
     precision: "fp32" (default); "bf16", "fp16" or "i16" (precision form: the cos/sin stack
     quantised to bfloat16, float16 or 16-bit fixed point, FP32 sums); "fp64" (img float64).
     N: None selects N_0(sigma_r, T).  weight_eps > 0 drops binomial weights below it.
+    block, strip_h, order_chunk: launch shape (0 = tuned or automatic).
     """
     dt = torch.float64 if precision == "fp64" else torch.float32
     _check_image(img, "img", dt)
@@ -85,7 +87,7 @@ def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, 
         if out.shape != img.shape:
             raise ValueError("out has the wrong shape")
     H, W = img.shape
-    opt = _options(N, precision, weight_eps, kahan, block, strip_h)
+    opt = _options(N, precision, weight_eps, kahan, block, strip_h, order_chunk)
     with torch.cuda.device(img.device):
         _lib.check(_lib.load().bilateral_shiftable_ex(
             ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),
@@ -164,19 +166,19 @@ def bilateral_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas
 
 def autotune(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,
              precision: str = "fp32", weight_eps: float = 0.0, kahan: bool = False, path: Optional[str] = None):
-    """Times the launch shapes for this request and caches the fastest; returns (block, rows, ms)."""
+    """Times the launch shapes for this request and caches the fastest; returns (block, rows, chunk, ms)."""
     dt = torch.float64 if precision == "fp64" else torch.float32
     _check_image(img, "img", dt)
     out = torch.empty_like(img)
     H, W = img.shape
     opt = _options(N, precision, weight_eps, kahan)
-    b, s, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+    b, s, k, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
     with torch.cuda.device(img.device):
         _lib.check(_lib.load().bsk_autotune(
             ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),
             ctypes.c_void_p(out.data_ptr()), ctypes.byref(opt), path.encode() if path else None, _stream(),
-            ctypes.byref(b), ctypes.byref(s), ctypes.byref(ms)))
-    return b.value, s.value, ms.value
+            ctypes.byref(b), ctypes.byref(s), ctypes.byref(k), ctypes.byref(ms)))
+    return b.value, s.value, k.value, ms.value
 
 
 def release():
