@@ -180,13 +180,18 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     } else if (tuned_S > 0) {
         r->S = tuned_S;
     } else {
-        // about four workgroups per compute unit (one resident at a time)
-        const int target = 4 * device_cus();
-        int segs = (target + strips - 1) / strips;
+        // Rows per workgroup: about two full rounds of resident workgroups
+        // (three per compute unit for the 256-lane FP32 forward, two otherwise).
+        // Fewer, taller workgroups leave compute units idle or without a second
+        // resident workgroup to overlap with; shorter ones repeat the 2 rv rows
+        // of window initialisation more often.
+        const int bpc = (block == 256 && r->prec != BSK_FP64 && !r->kahan) ? 3 : 2;
+        const long long target = 2LL * bpc * device_cus();
+        long long segs = (target + strips - 1) / strips;
         if (segs < 1) segs = 1;
-        int S = (H + segs - 1) / segs;
-        if (S < 16) S = 16;
-        r->S = S;
+        int bestS = (int)((H + segs - 1) / segs);
+        if (bestS < 8) bestS = 8;
+        r->S = bestS;
     }
     if (r->S > H) r->S = H;
     return BSK_OK;

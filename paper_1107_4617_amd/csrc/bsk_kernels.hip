@@ -24,8 +24,11 @@ constexpr int kl_train(int block) { return kr_train(block) / 2; }
 template <int NCH, int KL, int BLOCK, typename AT>
 constexpr int lds_elems() { return NCH * KL * (BLOCK + pow2_floor(BLOCK / (NCH * KL))); }
 
-template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
-__global__ void __launch_bounds__(BLOCK, lds_occupancy(lds_elems<POL::NCH, KL, BLOCK, AT>() * (int)sizeof(AT)))
+// MINB: workgroups per compute unit the register allocation targets (0: the
+// LDS-derived default).
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
+__global__ void __launch_bounds__(BLOCK, MINB ? MINB : lds_occupancy(lds_elems<POL::NCH, KL, BLOCK, AT>() *
+                                                                     (int)sizeof(AT)))
     strip_kernel(const StripArgs a)
 {
     __shared__ AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
@@ -89,13 +92,13 @@ __global__ void __launch_bounds__(256) sigma_reduce_kernel(const float *unused, 
 }
 
 // ---------------------------------------------------------------- launches --
-template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
 static hipError_t launch(const StripArgs &a, hipStream_t s)
 {
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
-    hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>), grid, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -115,8 +118,10 @@ template <int BLOCK, int QUANT, bool KAHAN>
 static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s)
 {
     constexpr int KR = kr_f32(BLOCK), KL = kl_f32(BLOCK);
-    if (kc == KR) return launch<float, BLOCK, KR, KL, PolForward<float>, QUANT, KAHAN>(a, s);
-    return launch<float, BLOCK, KL, KL, PolForward<float>, QUANT, KAHAN>(a, s);
+    // three workgroups per compute unit where the registers allow it
+    constexpr int MINB = (BLOCK == 256 && !KAHAN) ? 3 : 0;
+    if (kc == KR) return launch<float, BLOCK, KR, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
+    return launch<float, BLOCK, KL, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
 }
 
 template <int QUANT, bool KAHAN>
