@@ -6,9 +6,11 @@ transforms, horizontal and vertical moving sums, recombination, ratio) over a
 box radius 20, sigma_r = 30, T = 255, N = 30 (16 folded orders).  Inputs are
 resident in HBM before timing starts; steps are timed with HIP events on the
 stream the library launches on.  The same run also times, at their own
-workloads, the training forward + adjoint, the BF16 precision form and the
-batched persistent/graph launch, and the FP64 CPU oracle on a bounded sample
-of the headline workload (reported as cpu_baseline).
+workloads, the training forward + adjoint, the 16-bit precision forms (BF16,
+FP16, Q15 stack; with and without Kahan-compensated sums), the 8192^2 r=32
+workload, the 16 x 1024^2 differentiation workload and the batched
+persistent/graph launch, and the FP64 CPU oracle on a bounded sample of the
+headline workload (reported as cpu_baseline).
 
 Prints ONE JSON line.
 """
@@ -33,6 +35,7 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 # running-sum updates 16, recombination of P and Q 10.
 FLOP_PER_PX_ORDER = 34
 BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
+METRIC = "Mpixel/s + %HBM roofline, 4096\u00b2 r=20 \u03c3r=30; fwd+bwd and BF16 vs plain FP32"
 
 
 def log(msg):
@@ -83,6 +86,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="profiling mode: run the headline forward --steps times (after --warmup) and a "
+                         "device copy of --copy-mib MiB, print nothing but a summary line")
+    ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -106,6 +113,20 @@ def main():
     out = torch.empty_like(img)
 
     fwd = lambda: bilateral(img, radius, sigma, T, N=N, out=out)  # noqa: E731
+    if args.kernel_only:
+        # a plain device copy of known size: reference for the HBM byte counters
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        for _ in range(args.warmup):
+            fwd()
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            fwd()
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": True, "steps": args.steps, "copy_bytes": 4 * n}), flush=True)
+        return
     log("timing FP32 forward")
     mean_ms, med_ms, wall = time_calls(fwd, args.steps, args.warmup, stream)
     px = H * W
@@ -113,7 +134,7 @@ def main():
     flops = FLOP_PER_PX_ORDER * K * px
     achieved = flops / (mean_ms * 1e-3) / 1e12
     rec = {
-        "metric": "Mpixel/s + %HBM roofline, 4096^2 r=20 sigma_r=30 (plain FP32 forward)",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -134,7 +155,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": None,
-            "kernel": "strip_kernel<float,256,16,PolForward>",
+            "kernel": "strip_kernel<float,256,16,8,PolForward<float>,0,false,3>",
             "flop_per_launch": flops,
             "hbm_frac": round(BYTES_PER_PX * px / (mean_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         },
@@ -143,18 +164,23 @@ def main():
 
     if not args.no_extra:
         variants = {}
-        # BF16 precision form at the headline workload (weights below 1e-7 dropped)
+        # precision forms at the headline workload: the cos/sin stack quantised to
+        # 16 bits, Kahan-compensated vertical sums, weights below 1e-7 dropped
         kb, eps = plan_info(N, 1e-7)
-        outb = torch.empty_like(img)
-        log("timing BF16 precision form")
-        ms_b, _, _ = time_calls(lambda: bilateral(img, radius, sigma, T, N=N, precision="bf16", weight_eps=1e-7,
-                                                  kahan=True, out=outb), args.steps, args.warmup, stream)
-        variants["bf16_kahan_trunc1e-7"] = {"Mpixel/s": round(px / ms_b / 1e3, 2), "ms": round(ms_b, 4),
-                                            "folded_orders": kb, "dropped_weight": eps,
-                                            "max_abs_vs_fp32": float((outb - out).abs().max())}
+        outq = torch.empty_like(img)
+        for prec in ("bf16", "fp16", "i16"):
+            for kahan in (True, False):
+                log(f"timing {prec} precision form, kahan={kahan}")
+                ms_q, _, _ = time_calls(lambda: bilateral(img, radius, sigma, T, N=N, precision=prec,
+                                                          weight_eps=1e-7, kahan=kahan, out=outq),
+                                        args.steps, args.warmup, stream)
+                name = f"{prec}{'_kahan' if kahan else ''}_trunc1e-7"
+                variants[name] = {"Mpixel/s": round(px / ms_q / 1e3, 2), "ms": round(ms_q, 4),
+                                  "folded_orders": kb, "dropped_weight": eps,
+                                  "max_abs_vs_fp32": float((outq - out).abs().max())}
+        del outq
         # training forward + adjoint at the headline workload
         g = torch.randn_like(img)
-        holder = {}
 
         def fb():
             o, s = bilateral_train(img, radius, sigma, T, N)
@@ -163,7 +189,24 @@ def main():
         log("timing forward+backward")
         ms_fb, _, _ = time_calls(fb, max(3, args.steps // 2), 1, stream)
         variants["fwd_bwd_fp32"] = {"Mpixel/s": round(px / ms_fb / 1e3, 2), "ms": round(ms_fb, 4)}
-        del g, holder
+        del g
+        # 8192^2, r=32, sigma_r=15, N=117: plain FP32 (59 orders) vs 16-bit stack + truncation (28 orders)
+        log("timing 8192^2 r=32 workload")
+        big = torch.from_numpy(wl.rect_image(8192, 8192, seed=3)).to(dev)
+        outb = torch.empty_like(big)
+        ms_p, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, out=outb), 3, 1, stream)
+        ms_i, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, precision="i16", weight_eps=1e-7,
+                                                  kahan=True, out=outb), 3, 1, stream)
+        ms_n, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, precision="i16", weight_eps=1e-7,
+                                                  out=outb), 3, 1, stream)
+        px8 = 8192 * 8192
+        variants["rect8192_r32_s15"] = {"fp32_Mpixel/s": round(px8 / ms_p / 1e3, 2),
+                                        "fp32_ms": round(ms_p, 3), "fp32_orders": plan_info(117, 0.0)[0],
+                                        "i16_kahan_trunc_Mpixel/s": round(px8 / ms_i / 1e3, 2),
+                                        "i16_kahan_trunc_ms": round(ms_i, 3),
+                                        "i16_trunc_Mpixel/s": round(px8 / ms_n / 1e3, 2),
+                                        "i16_trunc_ms": round(ms_n, 3), "i16_orders": plan_info(117, 1e-7)[0]}
+        del big, outb
         # differentiation workload: 16 x 1024^2, r=10, sigma_r=25, N=43
         log("timing 16x1024^2 fwd+bwd")
         pairs = [wl.denoise_pair(i) for i in range(16)]
@@ -180,7 +223,7 @@ def main():
         variants["denoise16x1024_fwd_bwd"] = {"Mpixel/s": round(16 * 1024 * 1024 / ms16 / 1e3, 2),
                                               "ms": round(ms16, 3)}
         del xs, ts, pairs
-        # batched workload: 256 images, graph replay
+        # batched workload: 256 images, one persistent launch replayed from a HIP graph
         log("generating 256-image batch")
         specs = wl.batch_specs(256, seed=4)
         imgs = [torch.from_numpy(wl.gradient_image(h, w, s)).to(dev) for (h, w, r, sg, s) in specs]

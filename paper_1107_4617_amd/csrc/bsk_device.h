@@ -70,6 +70,31 @@ __device__ __forceinline__ void fast_sincos(float x, float *s, float *c)
     *c = ((q + 1) & 2) ? -cv : cv;
 }
 __device__ __forceinline__ void sc(float x, float *s, float *c) { fast_sincos(x, s, c); }
+
+// sin and cos of y for |y| <= pi/2: the Taylor polynomials to degree 11 and 12
+// (truncation error below 6e-8 at |y| = pi/2), no reduction.  Lanes with
+// |y| > pi/2 (data beyond the range bound) take the reducing path instead.
+__device__ __forceinline__ void sincos_small(float y, float *s, float *c)
+{
+    if (fabsf(y) > 1.57079637f) {
+        fast_sincos(y, s, c);
+        return;
+    }
+    const float y2 = y * y;
+    float ps = __builtin_fmaf(y2, -2.50521083854417188e-8f, 2.75573192239858907e-6f);
+    ps = __builtin_fmaf(y2, ps, -1.98412698412698413e-4f);
+    ps = __builtin_fmaf(y2, ps, 8.33333333333333333e-3f);
+    ps = __builtin_fmaf(y2, ps, -1.66666666666666667e-1f);
+    *s = __builtin_fmaf(y * y2, ps, y);
+    float pc = __builtin_fmaf(y2, 2.08767569878680990e-9f, -2.75573192239858907e-7f);
+    pc = __builtin_fmaf(y2, pc, 2.48015873015873016e-5f);
+    pc = __builtin_fmaf(y2, pc, -1.38888888888888889e-3f);
+    pc = __builtin_fmaf(y2, pc, 4.16666666666666667e-2f);
+    pc = __builtin_fmaf(y2, pc, -0.5f);
+    *c = __builtin_fmaf(y2, pc, 1.0f);
+}
+__device__ __forceinline__ void sc_small(float y, float *s, float *c) { sincos_small(y, s, c); }
+__device__ __forceinline__ void sc_small(double y, double *s, double *c) { sincos(y, s, c); }
 // fused multiply-add in the type of its arguments
 __device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -92,26 +117,24 @@ __device__ __forceinline__ double quant(double x) { return x; }
 // cos and sin of (omega_0 + m delta) g for m = 0, 1, ... by the three-term
 // recurrence x_{m+1} = 2 cos(delta g) x_m - x_{m-1}, which both sequences
 // satisfy (angle addition); one fused multiply-add per value and order.  The
-// start needs one sincos when omega_0 is 0 or delta / 2 (the first pass of an
-// even or odd order: the half-angle gives the step), two otherwise.  A pixel
-// outside the image starts at zero so all its channels vanish.
+// start needs one sincos of the half step angle when omega_0 is 0 or delta / 2
+// (the first pass of an even or odd order), two general sincos otherwise.  A
+// pixel outside the image starts at zero so all its channels vanish.
 template <typename AT>
 struct Chain {
     AT c, s, cp, sp, a2;   // current, previous, 2 cos(delta g)
     __device__ __forceinline__ void start(bool valid, AT g, AT om0, AT dlt, int mode)
     {
         AT c0, s0, cd, sd;
-        if (mode == 0) {            // omega_0 = 0
-            sc(dlt * g, &sd, &cd);
-            c0 = AT(1);
-            s0 = AT(0);
-        } else if (mode == 1) {     // omega_0 = delta / 2
+        if (mode <= 1) {
+            // the half step angle y = delta g / 2 (= omega_0 g when omega_0 = delta / 2),
+            // then the step by the double-angle formulas
             AT sh, ch;
-            sc(om0 * g, &sh, &ch);
-            c0 = ch;
-            s0 = sh;
-            cd = AT(1) - AT(2) * sh * sh;
+            sc_small(AT(0.5) * dlt * g, &sh, &ch);
+            cd = fmat(AT(-2) * sh, sh, AT(1));
             sd = AT(2) * sh * ch;
+            c0 = mode == 0 ? AT(1) : ch;
+            s0 = mode == 0 ? AT(0) : sh;
         } else {
             sc(om0 * g, &s0, &c0);
             sc(dlt * g, &sd, &cd);
