@@ -155,7 +155,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": None,
-            "kernel": "strip_kernel<float,256,16,8,PolForward<float>,0,false,3>",
+            "kernel": "strip_kernel<float,256,16,4,PolForward<float>,0,false,3>",
             "flop_per_launch": flops,
             "hbm_frac": round(BYTES_PER_PX * px / (mean_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         },

@@ -180,14 +180,15 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     } else if (tuned_S > 0) {
         r->S = tuned_S;
     } else {
-        // Rows per workgroup: about two full rounds of resident workgroups
+        // Rows per workgroup: at most two full rounds of resident workgroups
         // (three per compute unit for the 256-lane FP32 forward, two otherwise).
         // Fewer, taller workgroups leave compute units idle or without a second
         // resident workgroup to overlap with; shorter ones repeat the 2 rv rows
-        // of window initialisation more often.
+        // of window initialisation more often.  The segment count rounds down,
+        // so a last, nearly empty round of workgroups never appears.
         const int bpc = (block == 256 && r->prec != BSK_FP64 && !r->kahan) ? 3 : 2;
         const long long target = 2LL * bpc * device_cus();
-        long long segs = (target + strips - 1) / strips;
+        long long segs = target / strips;
         if (segs < 1) segs = 1;
         int bestS = (int)((H + segs - 1) / segs);
         if (bestS < 8) bestS = 8;

@@ -219,8 +219,7 @@ int stage_upload(void *stream, const std::vector<char> &tab, void *dev_dst)
 
 int grid_for(int block)
 {
-    (void)block;
-    return 2 * device_cus();   // two resident workgroups per compute unit (LDS bound)
+    return bsk::wg_per_cu_batched(block) * device_cus();   // every resident workgroup slot
 }
 
 // ---------------------------------------------------------------- graphs --

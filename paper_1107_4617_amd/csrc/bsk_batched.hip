@@ -11,7 +11,11 @@ namespace bsk {
 
 // Same pass shapes as the single-image FP32 forward (full pass).
 constexpr int kc_batched(int block) { return block == 256 ? 16 : block == 512 ? 8 : 4; }
-constexpr int kl_batched(int block) { return kc_batched(block) / 2; }
+constexpr int kl_batched(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
+// resident workgroups per compute unit: three 256-lane ones (LDS and
+// registers), two of the wider ones
+constexpr int wg_batched(int block) { return block == 256 ? 3 : 2; }
+int wg_per_cu_batched(int block) { return wg_batched(block); }
 
 int chunk_batched_f32(int block) { return kc_batched(block); }
 int max_radius_batched(int block) { return (block - 2) / 2; }
@@ -19,10 +23,9 @@ int max_radius_batched(int block) { return (block - 2) / 2; }
 __global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
 
 template <int BLOCK, int KC>
-__global__ void __launch_bounds__(BLOCK, 2) batched_kernel(const BatchArgs a)
+__global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const BatchArgs a)
 {
-    constexpr int ROWS = PolForward<float>::NCH * kl_batched(BLOCK);
-    __shared__ float lds[ROWS * (BLOCK + pow2_floor(BLOCK / ROWS))];
+    __shared__ float lds[strip_lds_elems<PolForward<float>::NCH, kl_batched(BLOCK), BLOCK>()];
     __shared__ int unit_sh;
     for (;;) {
         if (threadIdx.x == 0) unit_sh = (int)atomicAdd(a.counter, 1u);

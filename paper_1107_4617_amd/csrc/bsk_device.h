@@ -40,6 +40,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+
 #include "bsk_internal.h"
 
 namespace bsk {
@@ -163,7 +164,9 @@ __device__ __forceinline__ T ld(const void *p, long idx) { return ((const T *)p)
 // ------------------------------------------------------------------ policies --
 // A policy fixes the channels that are box-summed per order, the raw per-pixel
 // inputs they need (fetched one row ahead), and how box sums recombine into
-// per-pixel accumulators.
+// per-pixel accumulators.  fetch always reads the in-image pixel (i, j) it is
+// given (callers clamp the indices) and replaces it by the value of an absent
+// pixel when valid is false, so that loads never need a branch.
 
 // Channels come in pairs (kappa_p C, kappa_p S) with a per-pixel coefficient
 // kappa_p; channel 2p is the cosine member and 2p+1 the sine member.
@@ -186,7 +189,8 @@ struct PolForward {
     template <typename AT>
     __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
     {
-        raw[0] = valid ? (AT)ld<FT>(a.img, (long)i * a.pitch_in + j) : AT(0);
+        const AT x = (AT)ld<FT>(a.img, (long)i * a.pitch_in + j);
+        raw[0] = valid ? x : AT(0);
     }
     template <typename AT>
     __device__ static void make(const AT *raw, AT ref, AT *aux)
@@ -238,7 +242,8 @@ struct PolTrain {
     template <typename AT>
     __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
     {
-        raw[0] = valid ? (AT)ld<float>(a.img, (long)i * a.pitch_in + j) : AT(0);
+        const AT x = (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
+        raw[0] = valid ? x : AT(0);
     }
     template <typename AT>
     __device__ static void make(const AT *raw, AT ref, AT *aux)
@@ -305,16 +310,13 @@ struct PolBackward {
     template <typename AT>
     __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
     {
-        if (valid) {
-            const long o = (long)i * a.W + j;
-            raw[0] = (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
-            raw[1] = (AT)a.aux0[o];
-            raw[2] = (AT)a.aux1[o];
-            raw[3] = (AT)a.aux2[o];
-        } else {
-            raw[0] = raw[1] = raw[3] = AT(0);
-            raw[2] = AT(1);
-        }
+        const long o = (long)i * a.W + j;
+        const AT x0 = (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
+        const AT x1 = (AT)a.aux0[o], x2 = (AT)a.aux1[o], x3 = (AT)a.aux2[o];
+        raw[0] = valid ? x0 : AT(0);
+        raw[1] = valid ? x1 : AT(0);
+        raw[2] = valid ? x2 : AT(1);
+        raw[3] = valid ? x3 : AT(0);
     }
     template <typename AT>
     __device__ static void make(const AT *raw, AT ref, AT *aux)
@@ -366,15 +368,82 @@ __device__ __forceinline__ float weight<float>(const Geom &gm, int m) { return g
 template <>
 __device__ __forceinline__ double weight<double>(const Geom &gm, int m) { return gm.v[m]; }
 
-// Walker geometry of one LDS row of BLOCK columns: CH walkers (a power of two,
-// at most one wavefront) per row, each owning G consecutive columns.  Column
-// col lives at col + col / G, so the row stride is BLOCK + CH; with CH walkers
-// per row and 64 / CH rows per wavefront the walkers' simultaneous accesses
-// fall on distinct banks.
-constexpr int pow2_floor(int x) { return x >= 64 ? 64 : x >= 32 ? 32 : x >= 16 ? 16 : x >= 8 ? 8 : x >= 4 ? 4 : x >= 2 ? 2 : 1; }
 
+// Walker geometry of one LDS row of BLOCK columns.  The row holds column c at
+// position c (a contiguous run of lanes touches distinct banks) and, after the
+// H stage, the exclusive prefix sum E(c) = sum_{j < c} V(j), for c = 0 .. BLOCK.
+// CH walkers (a power of two, at most one wavefront) per row each own G
+// consecutive positions, G odd: walker w starts at position G w, so the CH
+// walkers of a row start on distinct banks, and rows in the same half
+// wavefront are offset by RS = CH (mod 32) positions, which keeps their
+// banks disjoint.  The last walker's chunk runs past position BLOCK into the
+// row's tail; what it reads and writes there only feeds prefixes beyond BLOCK,
+// which nothing uses.
+constexpr int pow2_floor(int x) { return x >= 64 ? 64 : x >= 32 ? 32 : x >= 16 ? 16 : x >= 8 ? 8 : x >= 4 ? 4 : x >= 2 ? 2 : 1; }
+constexpr int walker_count(int block, int rows) { return pow2_floor(block / rows); }
+constexpr int walker_chunk(int block, int ch) { return (block / ch) % 2 == 0 ? block / ch + 1 : block / ch; }
+constexpr int row_stride(int block, int ch, int g)
+{
+    int rs = ch * g > block + 1 ? ch * g : block + 1;
+    if (ch < 32)
+        while (rs % 32 != ch) ++rs;
+    return rs;
+}
+
+// Floor division and the matching non-negative remainder, for the (possibly
+// negative) interval offsets of the pipeline stages.
+constexpr int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+constexpr int floormod(int a, int b) { return a - floordiv(a, b) * b; }
+
+// LDS row buffers of the pipeline: the V stage fills one while the H stage
+// scans the previous one and the R stage reads the one before that.
+constexpr int kNBuf = 3;
+template <int NCH, int KL, int BLOCK>
+constexpr int strip_lds_elems()
+{
+    return kNBuf * NCH * KL *
+           row_stride(BLOCK, walker_count(BLOCK, NCH * KL), walker_chunk(BLOCK, walker_count(BLOCK, NCH * KL)));
+}
+
+// Exclusive prefix sums over aligned groups of CH consecutive lanes (CH a power
+// of two, at most 64); wch is the lane's index in its group.  Groups of 16 are
+// DPP rows: four shifted adds within the row and one final shift, no LDS.
+template <int CH, typename AT>
+__device__ __forceinline__ AT group_exclusive_scan(AT x, int wch)
+{
+    if constexpr (CH == 16 && sizeof(AT) == 4) {
+        // row_shr:n (dpp_ctrl 0x110 + n) reads lane l - n of the same row; the
+        // first n lanes of the row read zero (bound_ctrl)
+        float y = x;
+        y += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x111, 0xf, 0xf, true));
+        y += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x112, 0xf, 0xf, true));
+        y += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x114, 0xf, 0xf, true));
+        y += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x118, 0xf, 0xf, true));
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x111, 0xf, 0xf, true));
+    } else {
+        // inclusive scan, then a shift by one lane (never inc - x: the last
+        // walker's total includes the unused tail of the row)
+        AT inc = x;
+#pragma unroll
+        for (int d = 1; d < CH; d <<= 1) {
+            const AT y = __shfl_up(inc, d, CH);
+            if (wch >= d) inc += y;
+        }
+        const AT prev = __shfl_up(inc, 1, CH);
+        return wch > 0 ? prev : AT(0);
+    }
+}
+
+// The strip body, software-pipelined over "intervals" of KL orders of one row.
+// Interval t runs three stages on three LDS row buffers (t mod 3):
+//   V (interval t)      vertical moving sums of the KL orders, written to buffer t;
+//   H (interval t - 1)  the walkers turn buffer t - 1 into prefix sums in place;
+//   R (interval t - 2)  output lanes read box sums from buffer t - 2 and
+//                       recombine them with the centre pixel's transforms;
+// then one workgroup barrier.  The stages touch different buffers, so each
+// interval mixes the VALU-heavy V stage with the LDS-heavy H and R stages.
 // KR orders are carried in registers per pass (the vertical sums of all their
-// channels); they go through LDS KL orders at a time (NCH * KL rows).
+// channels), NSUB = KR / KL intervals per row.
 template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
 __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, int by, AT *lds,
                                            double *red_lds, double *red_out)
@@ -385,14 +454,14 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     constexpr int NRAW = POL::NRAW;
     constexpr int NPAIR = POL::NPAIR;
     constexpr int ROWS = NCH * KL;
-    constexpr int CH = pow2_floor(BLOCK / ROWS);
-    constexpr int G = BLOCK / CH;
-    constexpr int RS = BLOCK + CH;
+    constexpr int CH = walker_count(BLOCK, ROWS);
+    constexpr int G = walker_chunk(BLOCK, CH);
+    constexpr int RS = row_stride(BLOCK, CH, G);
+    constexpr int BUF = ROWS * RS;
     constexpr int NSUB = KR / KL;
     static_assert(NCH == 2 * NPAIR, "channels come in (cos, sin) pairs");
     static_assert(KR % KL == 0, "KR must be a multiple of KL");
-    static_assert(CH * G == BLOCK && ROWS * CH <= BLOCK, "walker geometry");
-    AT *Vb = lds;
+    static_assert(CH * G >= BLOCK + 1 && RS >= CH * G && ROWS * CH <= BLOCK, "walker geometry");
 
     const int t = threadIdx.x;
     const int H = gm.H, W = gm.W, rh = gm.rh, rv = gm.rv;
@@ -408,20 +477,21 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     const AT ref = POL::template ref<AT>(a, i0, min(W - 1, j0 + Wt / 2));
     const long plane = (long)H * W;
 
-    // LDS positions: this lane's column (phase V), its walker chunk (phase H),
-    // and the two prefix positions its output needs (phase R)
-    const int vpos = t + t / G;
+    // LDS positions: this lane's column (V stage), its walker chunk (H stage),
+    // and the two prefix positions its output needs (R stage).  Rows are
+    // clamped into the image and columns to jxc so that every load is to an
+    // in-image address; absent pixels are masked by the policies' fetch.
+    const int jxc = min(max(jx, 0), W - 1);
+    auto rowc = [H](int y) { return min(max(y, 0), H - 1); };
+    const int vpos = t;
     const int wrow = t / CH;
     const int wch = t - wrow * CH;
-    const bool walker = wrow < ROWS;
-    const int wbase = wrow * RS + wch * (G + 1);
-    // P(-1) = 0 is read from a pad slot (position G of the row: never written
-    // by phase V or the walkers, zeroed below)
-    const int phi = (t + rh) + (t + rh) / G;
-    const int plo_col = t - rh - 1;
-    const int plo = plo_col >= 0 ? plo_col + plo_col / G : G;
-    if (walker) Vb[wrow * RS + wch * (G + 1) + G] = AT(0);
-    __syncthreads();
+    constexpr bool ALLWALK = ROWS * CH == BLOCK;
+    const bool walker = ALLWALK || wrow < ROWS;
+    const int wbase = wrow * RS + wch * G;
+    // box sum of output lane t: E(t + rh + 1) - E(t - rh)
+    const int phi = t + rh + 1;
+    const int plo = t - rh;
 
     double red = 0.0;
 
@@ -445,12 +515,12 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
         // initial window: rows [i0 - rv, i0 + rv - 1] (the first step adds i0 + rv)
         {
             AT raw[NRAW];
-            if (ylo < yhi) POL::template fetch<AT>(a, colok, ylo, jx, raw);
+            POL::template fetch<AT>(a, colok, rowc(ylo), jxc, raw);
             for (int y = ylo; y < yhi; ++y) {
                 AT aux[NAUX], kp[NPAIR];
                 POL::template make<AT>(raw, ref, aux);
                 POL::template kappa<AT>(aux, kp);
-                if (y + 1 < yhi) POL::template fetch<AT>(a, colok, y + 1, jx, raw);
+                POL::template fetch<AT>(a, colok, rowc(y + 1), jxc, raw);
                 Chain<AT> ch;
                 ch.start(colok, aux[0], om0, dlt, smode);
 #pragma unroll
@@ -466,137 +536,154 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
             }
         }
 
-        // raw inputs of the next row, fetched one row ahead
+        // raw inputs fetched one row ahead: incoming and outgoing rows for the
+        // V stage, the centre row for the R stage
         AT rin[NRAW], rout[NRAW], rc[NRAW];
         {
             const int yin = i0 + rv, yout = i0 - rv - 1;
-            POL::template fetch<AT>(a, colok && yin < H, yin, jx, rin);
-            POL::template fetch<AT>(a, colok && yout >= ylo, yout, jx, rout);
-            POL::template fetch<AT>(a, colok, i0, jx, rc);
+            POL::template fetch<AT>(a, colok && yin < H, rowc(yin), jxc, rin);
+            POL::template fetch<AT>(a, colok && yout >= ylo, rowc(yout), jxc, rout);
+            POL::template fetch<AT>(a, colok, i0, jxc, rc);
         }
-
-        for (int i = i0; i < i1; ++i) {
-            const int yin = i + rv, yout = i - rv - 1;
-            const bool vin = colok && (yin < H);
-            const bool vout = colok && (yout >= ylo);
-            AT auxi[NAUX], auxo[NAUX], auxc[NAUX], ki[NPAIR], ko[NPAIR];
-            POL::template make<AT>(rin, ref, auxi);
-            POL::template make<AT>(rout, ref, auxo);
-            POL::template make<AT>(rc, ref, auxc);
-            POL::template kappa<AT>(auxi, ki);
-            POL::template kappa<AT>(auxo, ko);
-            if (i + 1 < i1) {
-                POL::template fetch<AT>(a, colok && yin + 1 < H, yin + 1, jx, rin);
-                POL::template fetch<AT>(a, colok && yout + 1 >= ylo, yout + 1, jx, rout);
-                POL::template fetch<AT>(a, colok, i + 1, jx, rc);
-            }
-            Chain<AT> ci, co, cc;
-            ci.start(vin, auxi[0], om0, dlt, smode);
-            co.start(vout, auxo[0], om0, dlt, smode);
-            cc.start(colok, auxc[0], om0, dlt, smode);
-            AT acc[NACC];
+        Chain<AT> ci, co, cc;
+        AT ki[NPAIR], ko[NPAIR], auxc[NAUX], acc[NACC];
 #pragma unroll
-            for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
+        for (int p = 0; p < NPAIR; ++p) ki[p] = ko[p] = AT(0);
+#pragma unroll
+        for (int q = 0; q < NAUX; ++q) auxc[q] = AT(0);
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
+        int bv = 0;
 
+        // Interval (i, h): the V stage of sub-phase h of row i, the H stage one
+        // interval behind and the R stage two behind; the last interval with
+        // work is (i1 - i0) NSUB + 1.
+        const int iend = i1 + (NSUB >= 2 ? 1 : 2);
+        for (int i = i0; i < iend; ++i) {
 #pragma unroll
             for (int h = 0; h < NSUB; ++h) {
-                AT Cc[KL], Sc[KL];
-                // ---- phase V: vertical moving sums V += X(in) - X(out), transforms by rotation
-#pragma unroll
-                for (int k = 0; k < KL; ++k) {
-                    const int m = h * KL + k;
-                    const AT Ci = quant<QUANT>(ci.c), Si = quant<QUANT>(ci.s);
-                    const AT Co = quant<QUANT>(co.c), So = quant<QUANT>(co.s);
-#pragma unroll
-                    for (int p = 0; p < NPAIR; ++p) {
-                        if constexpr (KAHAN) {
-                            const AT x[2] = {ki[p] * Ci - ko[p] * Co, ki[p] * Si - ko[p] * So};
-#pragma unroll
-                            for (int e = 0; e < 2; ++e) {
-                                const int c = 2 * p + e;
-                                const AT y = x[e] - Cmp[m][c];
-                                const AT s = V[m][c] + y;
-                                Cmp[m][c] = (s - V[m][c]) - y;
-                                V[m][c] = s;
-                            }
-                        } else {
-                            V[m][2 * p] = fmat(-ko[p], Co, fmat(ki[p], Ci, V[m][2 * p]));
-                            V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) Vb[(k * NCH + c) * RS + vpos] = V[m][c];
-                    Cc[k] = quant<QUANT>(cc.c);
-                    Sc[k] = quant<QUANT>(cc.s);
-                    ci.step();
-                    co.step();
-                    cc.step();
-                }
-                __syncthreads();
+                const int iH = i + floordiv(h - 1, NSUB);
+                const int iR = i + floordiv(h - 2, NSUB);
+                const int sR = floormod(h - 2, NSUB);
+                const bool actV = i < i1;
+                const bool actH = iH >= i0 && iH < i1;
+                const bool actR = iR >= i0 && iR < i1;
+                // intervals past the last one with work do nothing (uniform)
+                if (!(actV || actH || actR)) continue;
+                const int bH = bv == 0 ? kNBuf - 1 : bv - 1;
+                const int bR = bH == 0 ? kNBuf - 1 : bH - 1;
+                AT *const VbV = lds + bv * BUF;
+                AT *const VbH = lds + bH * BUF;
+                const AT *const VbR = lds + bR * BUF;
 
-                // ---- phase H: each row's prefix sums, computed in place by CH walkers
-                {
-                    AT loc[G];
-                    AT run = AT(0);
-                    if (walker) {
+                // ---- R stage: box sums of the orders sR KL .. of row iR, recombined
+                if (actR && outlane) {
+                    if (sR == 0) {
+                        POL::template make<AT>(rc, ref, auxc);
+                        POL::template fetch<AT>(a, colok, rowc(iR + 1), jxc, rc);
+                        cc.start(colok, auxc[0], om0, dlt, smode);
 #pragma unroll
-                        for (int u = 0; u < G; ++u) loc[u] = Vb[wbase + u];
-#pragma unroll
-                        for (int u = 0; u < G; ++u) {
-                            run += loc[u];
-                            loc[u] = run;
-                        }
+                        for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
                     }
-                    // exclusive scan of the chunk totals over the row's CH lanes
-                    AT inc = run;
-#pragma unroll
-                    for (int d = 1; d < CH; d <<= 1) {
-                        const AT y = __shfl_up(inc, d, CH);
-                        if (wch >= d) inc += y;
-                    }
-                    const AT off = inc - run;
-                    if (walker) {
-#pragma unroll
-                        for (int u = 0; u < G; ++u) Vb[wbase + u] = loc[u] + off;
-                    }
-                }
-                __syncthreads();
-
-                // ---- phase R: box sums as prefix differences, recombined with the shift identity
-                if (outlane) {
 #pragma unroll
                     for (int k = 0; k < KL; ++k) {
-                        const int m = h * KL + k;
+                        const int m = sR * KL + k;
                         AT B[NCH];
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) {
-                            const AT *row = Vb + (k * NCH + c) * RS;
+                            const AT *row = VbR + (k * NCH + c) * RS;
                             B[c] = row[phi] - row[plo];
                         }
                         const AT v = weight<AT>(gm, m0 + m);
                         const AT vom = v * (om0 + (AT)m * dlt);
-                        POL::template recombine<AT>(v, vom, Cc[k], Sc[k], B, auxc, acc);
+                        POL::template recombine<AT>(v, vom, quant<QUANT>(cc.c), quant<QUANT>(cc.s), B, auxc, acc);
+                        cc.step();
                     }
                 }
-                // the next sub-phase overwrites the rows read above
-                if (NSUB > 1 && h + 1 < NSUB) __syncthreads();
-            }
 
-            if (outlane) {
-                const long o = (long)i * W + jx;
-                if (!first) {
+                // ---- H stage: every row of buffer t - 1 into its exclusive prefix sums, in place
+                if (actH) {
+                    AT loc[G];
+                    AT run = AT(0);
+                    if (walker) {
 #pragma unroll
-                    for (int q = 0; q < NACC; ++q) acc[q] += ((AT *)gm.ws)[q * plane + o];
-                }
-                if (last) {
-                    POL::template finalize<AT>(a, i, jx, ref, auxc, acc, &red);
-                } else {
+                        for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + u];
 #pragma unroll
-                    for (int q = 0; q < NACC; ++q) ((AT *)gm.ws)[q * plane + o] = acc[q];
+                        for (int u = 0; u < G; ++u) {
+                            const AT x = loc[u];
+                            loc[u] = run;
+                            run += x;
+                        }
+                    }
+                    const AT off = group_exclusive_scan<CH>(run, wch);
+                    if (walker) {
+#pragma unroll
+                        for (int u = 0; u < G; ++u) VbH[wbase + u] = loc[u] + off;
+                    }
                 }
+
+                // ---- V stage: vertical moving sums V += X(i + rv) - X(i - rv - 1)
+                if (actV) {
+                    if (h == 0) {
+                        const int yin = i + rv, yout = i - rv - 1;
+                        const bool vin = colok && (yin < H);
+                        const bool vout = colok && (yout >= ylo);
+                        AT auxi[NAUX], auxo[NAUX];
+                        POL::template make<AT>(rin, ref, auxi);
+                        POL::template make<AT>(rout, ref, auxo);
+                        POL::template kappa<AT>(auxi, ki);
+                        POL::template kappa<AT>(auxo, ko);
+                        POL::template fetch<AT>(a, colok && yin + 1 < H, rowc(yin + 1), jxc, rin);
+                        POL::template fetch<AT>(a, colok && yout + 1 >= ylo, rowc(yout + 1), jxc, rout);
+                        ci.start(vin, auxi[0], om0, dlt, smode);
+                        co.start(vout, auxo[0], om0, dlt, smode);
+                    }
+#pragma unroll
+                    for (int k = 0; k < KL; ++k) {
+                        const int m = h * KL + k;
+                        const AT Ci = quant<QUANT>(ci.c), Si = quant<QUANT>(ci.s);
+                        const AT Co = quant<QUANT>(co.c), So = quant<QUANT>(co.s);
+#pragma unroll
+                        for (int p = 0; p < NPAIR; ++p) {
+                            if constexpr (KAHAN) {
+                                const AT x[2] = {ki[p] * Ci - ko[p] * Co, ki[p] * Si - ko[p] * So};
+#pragma unroll
+                                for (int e = 0; e < 2; ++e) {
+                                    const int c = 2 * p + e;
+                                    const AT y = x[e] - Cmp[m][c];
+                                    const AT s = V[m][c] + y;
+                                    Cmp[m][c] = (s - V[m][c]) - y;
+                                    V[m][c] = s;
+                                }
+                            } else {
+                                V[m][2 * p] = fmat(-ko[p], Co, fmat(ki[p], Ci, V[m][2 * p]));
+                                V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) VbV[(k * NCH + c) * RS + vpos] = V[m][c];
+                        ci.step();
+                        co.step();
+                    }
+                }
+
+                // ---- row iR complete: continue or finish its accumulators
+                if (actR && sR == NSUB - 1 && outlane) {
+                    const long o = (long)iR * W + jx;
+                    if (!first) {
+#pragma unroll
+                        for (int q = 0; q < NACC; ++q) acc[q] += ((AT *)gm.ws)[q * plane + o];
+                    }
+                    if (last) {
+                        POL::template finalize<AT>(a, iR, jx, ref, auxc, acc, &red);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NACC; ++q) ((AT *)gm.ws)[q * plane + o] = acc[q];
+                    }
+                }
+                __syncthreads();
+                bv = bv == kNBuf - 1 ? 0 : bv + 1;
             }
-            // the next row's phase V overwrites the rows phase R just read
-            __syncthreads();
         }
     }
 

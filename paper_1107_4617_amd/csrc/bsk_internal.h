@@ -111,5 +111,6 @@ hipError_t launch_batched_f32(const BatchArgs &a, int block, int grid, hipStream
 int chunk_batched_f32(int block);
 // Largest clamped radius the batched kernel of a given block size accepts.
 int max_radius_batched(int block);
+int wg_per_cu_batched(int block);
 
 }  // namespace bsk

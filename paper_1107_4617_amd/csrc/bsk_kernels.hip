@@ -6,29 +6,36 @@
 namespace bsk {
 
 // Workgroups per compute unit that the LDS row buffers allow (160 KiB per CU).
-constexpr int lds_occupancy(int bytes) { return bytes <= 80 * 1024 ? 2 : 1; }
+constexpr int lds_occupancy(int bytes) { return bytes <= 160 * 1024 / 3 ? 3 : bytes <= 80 * 1024 ? 2 : 1; }
 
-// Pass shapes per lane count: orders in registers (full pass KR, half pass)
-// and orders per LDS sub-phase KL.  The LDS row buffer (NCH * KL rows of
-// BLOCK + CH elements) stays under 80 KiB, so at least two workgroups share a
-// compute unit.
+// Pass shapes per lane count: KR orders in registers per pass and KL orders per
+// pipeline interval (NCH * KL LDS rows per buffer).  The three row buffers stay
+// under 54 KiB where the lane count allows it, so three 256-lane workgroups
+// share a compute unit.  The half pass keeps KR / 2 orders in registers.
 constexpr int kr_f32(int block) { return block == 256 ? 16 : block == 512 ? 8 : 4; }
-constexpr int kl_f32(int block) { return kr_f32(block) / 2; }
+constexpr int kl_f32(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
 constexpr int kr_f64(int block) { return block == 256 ? 8 : block == 512 ? 4 : 1; }
-constexpr int kl_f64(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
-// the adjoint keeps fewer orders in registers (its policy needs more of them)
+constexpr int kl_f64(int block) { return block == 256 ? 2 : 1; }
+// the adjoint and the training forward keep fewer orders in registers (their
+// policies need more of them)
 constexpr int kr_bwd(int block) { return block == 256 ? 8 : block == 512 ? 8 : 2; }
-constexpr int kl_bwd(int block) { return block == 256 ? 8 : block == 512 ? 4 : 2; }
+constexpr int kl_bwd(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
 constexpr int kr_train(int block) { return block == 256 ? 10 : block == 512 ? 6 : 2; }
-constexpr int kl_train(int block) { return kr_train(block) / 2; }
+constexpr int kl_train(int block) { return block == 1024 ? 1 : 2; }
 template <int NCH, int KL, int BLOCK, typename AT>
-constexpr int lds_elems() { return NCH * KL * (BLOCK + pow2_floor(BLOCK / (NCH * KL))); }
+constexpr int lds_elems() { return strip_lds_elems<NCH, KL, BLOCK>(); }
+// workgroups per compute unit for the register allocation: what the LDS
+// allows, at most two (three only where asked for explicitly)
+template <int NCH, int KL, int BLOCK, typename AT>
+constexpr int default_minb()
+{
+    return lds_occupancy(lds_elems<NCH, KL, BLOCK, AT>() * (int)sizeof(AT)) >= 2 ? 2 : 1;
+}
 
 // MINB: workgroups per compute unit the register allocation targets (0: the
 // LDS-derived default).
 template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
-__global__ void __launch_bounds__(BLOCK, MINB ? MINB : lds_occupancy(lds_elems<POL::NCH, KL, BLOCK, AT>() *
-                                                                     (int)sizeof(AT)))
+__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, KL, BLOCK, AT>()))
     strip_kernel(const StripArgs a)
 {
     __shared__ AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
@@ -51,7 +58,7 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : lds_occupancy(lds_elems<P
 }
 
 template <int BLOCK, int KR, int KL>
-__global__ void __launch_bounds__(BLOCK, lds_occupancy(lds_elems<PolBackward::NCH, KL, BLOCK, float>() * 4))
+__global__ void __launch_bounds__(BLOCK, (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
     backward_kernel(const StripArgs a)
 {
     __shared__ float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
@@ -104,7 +111,7 @@ static hipError_t launch(const StripArgs &a, hipStream_t s)
 
 bool valid_chunk_forward_f32(int block, int kc)
 {
-    return kc == kr_f32(block) || kc == kl_f32(block);
+    return kc == kr_f32(block) || kc == kr_f32(block) / 2;
 }
 int chunk_forward_f32(int block) { return kr_f32(block); }
 int chunk_forward_f64(int block) { return kr_f64(block); }
@@ -121,7 +128,7 @@ static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s)
     // three workgroups per compute unit where the registers allow it
     constexpr int MINB = (BLOCK == 256 && !KAHAN) ? 3 : 0;
     if (kc == KR) return launch<float, BLOCK, KR, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
-    return launch<float, BLOCK, KL, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
+    return launch<float, BLOCK, KR / 2, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
 }
 
 template <int QUANT, bool KAHAN>
