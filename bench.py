@@ -35,6 +35,11 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 # running-sum updates 16, recombination of P and Q 10.
 FLOP_PER_PX_ORDER = 34
 BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
+# HBM bytes per launch of the headline kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a 256 MiB copy (profiles/strip_kernel_fwd_rect4096_r20_s30.md).
+# Valid for this kernel build only: set to None when the kernel changes.
+HEADLINE_KERNEL = "strip_kernel<float,256,16,4,PolForward<float>,0,false,3>"
+HEADLINE_HBM_BYTES = 369.5e6
 METRIC = "Mpixel/s + %HBM roofline, 4096\u00b2 r=20 \u03c3r=30; fwd+bwd and BF16 vs plain FP32"
 
 
@@ -82,8 +87,8 @@ def cpu_baseline(img, radius, sigma, N, budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--kernel-only", action="store_true",
@@ -154,9 +159,13 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None,
-            "kernel": "strip_kernel<float,256,16,4,PolForward<float>,0,false,3>",
+            "traffic": (round(HEADLINE_HBM_BYTES / (mean_ms * 1e-3) / 1e9, 1)
+                        if HEADLINE_HBM_BYTES is not None else None),
+            "traffic_unit": "GB/s",
+            "traffic_bytes_per_launch": HEADLINE_HBM_BYTES,
+            "kernel": HEADLINE_KERNEL,
             "flop_per_launch": flops,
+            "algorithmic_bytes_per_launch": BYTES_PER_PX * px,
             "hbm_frac": round(BYTES_PER_PX * px / (mean_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         },
         "median_ms": round(med_ms, 4),
