@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -95,7 +96,51 @@ int device_cus()
 // ----------------------------------------------------------- validation --
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r)
+// Orders per pass from the pass sizes a kernel family offers (full, full / 2):
+// the one with the lower estimated cost, counting the padded orders each pass
+// runs and about 2.5 + kc / 10 orders' worth of per-pass work (window
+// initialisation, recurrence starts, workspace traffic).
+static int pick_chunk(int K, int full)
+{
+    const int half = full / 2;
+    if (half < 1) return full;
+    auto cost = [K](int kc) { return ((K + kc - 1) / kc) * (kc + 2.5 + 0.1 * kc); };
+    return cost(half) < cost(full) ? half : full;
+}
+
+// Workgroups per compute unit of the kernel a resolved request will launch.
+static int kernel_occupancy(const Resolved &r, int kind)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(kind, r.block, r.kc, r.prec, r.kahan, [] {
+        int d = 0;
+        (void)hipGetDevice(&d);
+        return d;
+    }());
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    bsk::StripArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int occ = 1;
+    if (kind == kTrain) {
+        (void)bsk::launch_train_f32(a, r.block, nullptr, &occ);
+    } else if (kind == kBackward) {
+        (void)bsk::launch_backward_f32(a, r.block, r.kc, nullptr, 0.0, 0, nullptr, &occ);
+    } else if (r.prec == BSK_FP64) {
+        (void)bsk::launch_forward_f64(a, r.block, nullptr, &occ);
+    } else {
+        (void)bsk::launch_forward_f32(a, r.block, r.kc, r.prec, r.kahan, nullptr, &occ);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = occ;
+    return occ;
+}
+
+int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r, int kind)
 {
     if (H < 1 || W < 1) return fail(BSK_EINVAL, "image size %dx%d must be positive", H, W);
     if (radius < 0) return fail(BSK_EINVAL, "radius %d must be >= 0", radius);
@@ -138,7 +183,7 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
 
     int block = o.block;
     int tuned_S = 0, tuned_kc = 0;
-    if (o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
+    if (kind == kForward && o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
         int tb = 0, ts = 0, tk = 0;
         if (tuned_shape(r->rh, r->plan.K, H, W, r->prec, &tb, &ts, &tk)) {
             block = tb;
@@ -163,14 +208,19 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     r->block = block;
     if (o.order_chunk < 0) return fail(BSK_EINVAL, "order_chunk must be >= 0");
     int kc = o.order_chunk ? o.order_chunk : tuned_kc;
-    if (kc == 0) {
-        // the half pass when it holds every order (or for small order counts),
-        // else the full pass
-        const int full = bsk::chunk_forward_f32(block);
-        kc = (r->plan.K <= full / 2) ? full / 2 : full;
+    if (kind == kTrain) {
+        kc = bsk::chunk_train_f32(block);
+    } else if (kind == kBackward) {
+        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_backward_f32(block));
+        if (!bsk::valid_chunk_backward_f32(block, kc))
+            return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
+    } else if (r->prec == BSK_FP64) {
+        kc = bsk::chunk_forward_f64(block);
+    } else {
+        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_forward_f32(block));
+        if (!bsk::valid_chunk_forward_f32(block, kc))
+            return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     }
-    if (!bsk::valid_chunk_forward_f32(block, kc))
-        return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     r->kc = kc;
     if (o.strip_h < 0) return fail(BSK_EINVAL, "strip_h must be >= 0");
     const int Wt = block - 2 * r->rh;
@@ -180,13 +230,13 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     } else if (tuned_S > 0) {
         r->S = tuned_S;
     } else {
-        // Rows per workgroup: at most two full rounds of resident workgroups
-        // (three per compute unit for the 256-lane FP32 forward, two otherwise).
-        // Fewer, taller workgroups leave compute units idle or without a second
-        // resident workgroup to overlap with; shorter ones repeat the 2 rv rows
-        // of window initialisation more often.  The segment count rounds down,
-        // so a last, nearly empty round of workgroups never appears.
-        const int bpc = (block == 256 && r->prec != BSK_FP64 && !r->kahan) ? 3 : 2;
+        // Rows per workgroup: at most two full rounds of resident workgroups of
+        // the kernel that will run.  Fewer, taller workgroups leave compute
+        // units idle or without a second resident workgroup to overlap with;
+        // shorter ones repeat the 2 rv rows of window initialisation more
+        // often.  The segment count rounds down, so a last, nearly empty round
+        // of workgroups never appears.
+        const int bpc = kernel_occupancy(*r, kind);
         const long long target = 2LL * bpc * device_cus();
         long long segs = target / strips;
         if (segs < 1) segs = 1;
@@ -244,13 +294,13 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
 {
     if (!img || !out) return fail(BSK_EINVAL, "null image pointer");
     Resolved r;
-    int st = resolve(H, W, radius, sigma_r, T, opt, &r);
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kForward);
     if (st) return st;
     const size_t esz = r.prec == BSK_FP64 ? 8 : 4;
     if (overlap(img, ((size_t)(H - 1) * r.pitch_in + W) * esz, out, ((size_t)(H - 1) * r.pitch_out + W) * esz))
         return fail(BSK_EINVAL, "img and out overlap");
     bsk::StripArgs a;
-    const int kc = r.prec == BSK_FP64 ? bsk::chunk_forward_f64(r.block) : r.kc;
+    const int kc = r.kc;
     fill_args(&a, r, H, W, kc);
     a.io.img = img;
     a.io.out = out;
@@ -270,11 +320,11 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
 int train_impl(const float *img, int H, int W, const Resolved &r, float *out, float *saved, void *stream)
 {
     bsk::StripArgs a;
-    fill_args(&a, r, H, W, bsk::chunk_train_f32(r.block));
+    fill_args(&a, r, H, W, r.kc);
     a.io.img = img;
     a.io.out = out;
     a.io.out2 = saved;
-    if (r.plan.K > bsk::chunk_train_f32(r.block)) {
+    if (r.plan.K > r.kc) {
         void *ws = nullptr;
         int st = get_ws(stream, 1, (size_t)bsk::acc_count_train() * H * W * 4, &ws);
         if (st) return st;
@@ -309,7 +359,7 @@ int bilateral_shiftable_train(const float *img, int H, int W, int radius, float 
 {
     if (!img || !out || !saved) return fail(BSK_EINVAL, "null pointer");
     Resolved r;
-    int st = resolve(H, W, radius, sigma_r, T, opt, &r);
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kTrain);
     if (st) return st;
     if (r.prec != BSK_FP32 || r.kahan)
         return fail(BSK_EUNSUPPORTED, "the training forward is FP32 without compensation");
@@ -327,7 +377,7 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
     if (!img || !grad_out) return fail(BSK_EINVAL, "null pointer");
     if ((out == nullptr) != (saved == nullptr)) return fail(BSK_EINVAL, "out and saved must both be given or both NULL");
     Resolved r;
-    int st = resolve(H, W, radius, sigma_r, T, opt, &r);
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kBackward);
     if (st) return st;
     if (r.prec != BSK_FP32 || r.kahan) return fail(BSK_EUNSUPPORTED, "the adjoint is FP32");
     if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "the adjoint needs dense pitch");
@@ -342,13 +392,17 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
         if (st) return st;
         float *u = (float *)tmp;
         float *sv = u + (size_t)H * W;
-        st = train_impl(img, H, W, r, u, sv, stream);
+        // the training forward with its own launch shape
+        Resolved rt;
+        st = resolve(H, W, radius, sigma_r, T, opt, &rt, kTrain);
+        if (st) return st;
+        st = train_impl(img, H, W, rt, u, sv, stream);
         if (st) return st;
         out = u;
         saved = sv;
     }
     bsk::StripArgs a;
-    fill_args(&a, r, H, W, bsk::chunk_backward_f32(r.block));
+    fill_args(&a, r, H, W, r.kc);
     a.io.img = img;
     a.io.aux0 = grad_out;
     a.io.aux1 = saved;                      // Q
@@ -361,13 +415,13 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
     st = get_ws(stream, 3, (size_t)nred * sizeof(double), &red);
     if (st) return st;
     a.red = (double *)red;
-    if (r.plan.K > bsk::chunk_backward_f32(r.block)) {
+    if (r.plan.K > r.kc) {
         void *ws = nullptr;
         st = get_ws(stream, 4, (size_t)bsk::acc_count_backward() * H * W * 4, &ws);
         if (st) return st;
         a.ws = ws;
     }
-    hipError_t e = bsk::launch_backward_f32(a, r.block, grad_sigma, 1.0 / (double)sigma_r, nred,
+    hipError_t e = bsk::launch_backward_f32(a, r.block, r.kc, grad_sigma, 1.0 / (double)sigma_r, nred,
                                             (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return BSK_OK;

@@ -22,12 +22,16 @@ struct Resolved {
     int pitch_in, pitch_out;
     int rh, rv;
     int block;
-    int kc;        // FP32 forward orders per pass (other kernels use their own)
+    int kc;        // orders per pass of the kernel the request runs
     int S;
     bsk::Plan plan;
 };
 
-int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r);
+// The kernel family a request is resolved for: its pass sizes and residency
+// set the orders per pass and the segment height.
+enum Kind { kForward = 0, kTrain = 1, kBackward = 2 };
+int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r,
+            int kind = kForward);
 // Fills the launch arguments; the weights are padded with zeros to a multiple
 // of `kc` (the pass size of the kernel that will run).
 void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W, int kc);

@@ -65,17 +65,20 @@ struct StripArgs {
 };
 
 // Launch helpers implemented in bsk_kernels.hip.  `prec` selects the stack
-// quantisation (bsk_precision) for the FP32 kernels.
-hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s);
-hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s);
-hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s);
-hipError_t launch_backward_f32(const StripArgs &a, int block, float *grad_sigma, double inv_sigma,
-                               int nred, hipStream_t s);
+// quantisation (bsk_precision) for the FP32 kernels.  With occ non-null a
+// helper launches nothing and stores in *occ the number of workgroups of the
+// kernel it would launch that one compute unit holds.
+hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s,
+                              int *occ = nullptr);
+hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
+hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
+hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
+                               int nred, hipStream_t s, int *occ = nullptr);
 
 // Orders per pass of the strip kernel for a kernel family/block; the FP32
-// forward offers two pass sizes per block (the smaller one halves the LDS
-// footprint, letting two workgroups share a compute unit).
+// forward and the adjoint offer a full and a half pass size per block.
 bool valid_chunk_forward_f32(int block, int kc);
+bool valid_chunk_backward_f32(int block, int kc);
 int chunk_forward_f32(int block);
 int chunk_forward_f64(int block);
 int chunk_train_f32(int block);

@@ -16,11 +16,12 @@ constexpr int kr_f32(int block) { return block == 256 ? 16 : block == 512 ? 8 : 
 constexpr int kl_f32(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
 constexpr int kr_f64(int block) { return block == 256 ? 8 : block == 512 ? 4 : 1; }
 constexpr int kl_f64(int block) { return block == 256 ? 2 : 1; }
-// the adjoint and the training forward keep fewer orders in registers (their
-// policies need more of them)
-constexpr int kr_bwd(int block) { return block == 256 ? 8 : block == 512 ? 8 : 2; }
+// The adjoint offers a full and a half pass like the forward (the half pass
+// of 256 lanes keeps three workgroups per CU).  The training forward box-sums
+// six channels; eight orders per pass keep three 256-lane workgroups per CU.
+constexpr int kr_bwd(int block) { return block == 256 ? 16 : block == 512 ? 8 : 2; }
 constexpr int kl_bwd(int block) { return block == 256 ? 4 : block == 512 ? 2 : 1; }
-constexpr int kr_train(int block) { return block == 256 ? 10 : block == 512 ? 6 : 2; }
+constexpr int kr_train(int block) { return block == 256 ? 8 : block == 512 ? 6 : 2; }
 constexpr int kl_train(int block) { return block == 1024 ? 1 : 2; }
 template <int NCH, int KL, int BLOCK, typename AT>
 constexpr int lds_elems() { return strip_lds_elems<NCH, KL, BLOCK>(); }
@@ -57,8 +58,8 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, K
     strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, blockIdx.x, blockIdx.y, lds, nullptr, nullptr);
 }
 
-template <int BLOCK, int KR, int KL>
-__global__ void __launch_bounds__(BLOCK, (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
+template <int BLOCK, int KR, int KL, int MINB = 0>
+__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
     backward_kernel(const StripArgs a)
 {
     __shared__ float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
@@ -99,9 +100,20 @@ __global__ void __launch_bounds__(256) sigma_reduce_kernel(const float *unused, 
 }
 
 // ---------------------------------------------------------------- launches --
-template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
-static hipError_t launch(const StripArgs &a, hipStream_t s)
+// Every launch helper either launches (occ == nullptr) or reports, in *occ,
+// how many workgroups of that exact kernel one compute unit holds.
+static hipError_t query_occupancy(const void *kernel, int block, int *occ)
 {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0);
+    *occ = (e == hipSuccess && n > 0) ? n : 1;
+    return e;
+}
+
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
+static hipError_t launch(const StripArgs &a, hipStream_t s, int *occ)
+{
+    if (occ) return query_occupancy((const void *)strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB>, BLOCK, occ);
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
@@ -113,6 +125,10 @@ bool valid_chunk_forward_f32(int block, int kc)
 {
     return kc == kr_f32(block) || kc == kr_f32(block) / 2;
 }
+bool valid_chunk_backward_f32(int block, int kc)
+{
+    return kc == kr_bwd(block) || kc == kr_bwd(block) / 2;
+}
 int chunk_forward_f32(int block) { return kr_f32(block); }
 int chunk_forward_f64(int block) { return kr_f64(block); }
 int chunk_train_f32(int block) { return kr_train(block); }
@@ -122,76 +138,87 @@ int acc_count_train() { return PolTrain::NACC; }
 int acc_count_backward() { return PolBackward::NACC; }
 
 template <int BLOCK, int QUANT, bool KAHAN>
-static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s)
+static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
     constexpr int KR = kr_f32(BLOCK), KL = kl_f32(BLOCK);
     // three workgroups per compute unit where the registers allow it
     constexpr int MINB = (BLOCK == 256 && !KAHAN) ? 3 : 0;
-    if (kc == KR) return launch<float, BLOCK, KR, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
-    return launch<float, BLOCK, KR / 2, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s);
+    if (kc == KR) return launch<float, BLOCK, KR, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s, occ);
+    return launch<float, BLOCK, KR / 2, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s, occ);
 }
 
 template <int QUANT, bool KAHAN>
-static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s)
+static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
     switch (block) {
-    case 256: return fwd32_block<256, QUANT, KAHAN>(a, kc, s);
-    case 512: return fwd32_block<512, QUANT, KAHAN>(a, kc, s);
-    case 1024: return fwd32_block<1024, QUANT, KAHAN>(a, kc, s);
+    case 256: return fwd32_block<256, QUANT, KAHAN>(a, kc, s, occ);
+    case 512: return fwd32_block<512, QUANT, KAHAN>(a, kc, s, occ);
+    case 1024: return fwd32_block<1024, QUANT, KAHAN>(a, kc, s, occ);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s)
+hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s, int *occ)
 {
     if (!valid_chunk_forward_f32(block, kc)) return hipErrorInvalidValue;
-    if (prec == 1) return kahan ? fwd32<1, true>(a, block, kc, s) : fwd32<1, false>(a, block, kc, s);
-    if (prec == 2) return kahan ? fwd32<2, true>(a, block, kc, s) : fwd32<2, false>(a, block, kc, s);
-    if (prec == 4) return kahan ? fwd32<4, true>(a, block, kc, s) : fwd32<4, false>(a, block, kc, s);
-    return kahan ? fwd32<0, true>(a, block, kc, s) : fwd32<0, false>(a, block, kc, s);
+    if (prec == 1) return kahan ? fwd32<1, true>(a, block, kc, s, occ) : fwd32<1, false>(a, block, kc, s, occ);
+    if (prec == 2) return kahan ? fwd32<2, true>(a, block, kc, s, occ) : fwd32<2, false>(a, block, kc, s, occ);
+    if (prec == 4) return kahan ? fwd32<4, true>(a, block, kc, s, occ) : fwd32<4, false>(a, block, kc, s, occ);
+    return kahan ? fwd32<0, true>(a, block, kc, s, occ) : fwd32<0, false>(a, block, kc, s, occ);
 }
 
-hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s)
+hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int *occ)
 {
     switch (block) {
-    case 256: return launch<double, 256, kr_f64(256), kl_f64(256), PolForward<double>, 0, false>(a, s);
-    case 512: return launch<double, 512, kr_f64(512), kl_f64(512), PolForward<double>, 0, false>(a, s);
-    case 1024: return launch<double, 1024, kr_f64(1024), kl_f64(1024), PolForward<double>, 0, false>(a, s);
+    case 256: return launch<double, 256, kr_f64(256), kl_f64(256), PolForward<double>, 0, false>(a, s, occ);
+    case 512: return launch<double, 512, kr_f64(512), kl_f64(512), PolForward<double>, 0, false>(a, s, occ);
+    case 1024: return launch<double, 1024, kr_f64(1024), kl_f64(1024), PolForward<double>, 0, false>(a, s, occ);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s)
+hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *occ)
 {
     switch (block) {
-    case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false>(a, s);
-    case 512: return launch<float, 512, kr_train(512), kl_train(512), PolTrain, 0, false>(a, s);
-    case 1024: return launch<float, 1024, kr_train(1024), kl_train(1024), PolTrain, 0, false>(a, s);
+    case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3>(a, s, occ);
+    case 512: return launch<float, 512, kr_train(512), kl_train(512), PolTrain, 0, false>(a, s, occ);
+    case 1024: return launch<float, 1024, kr_train(1024), kl_train(1024), PolTrain, 0, false>(a, s, occ);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int BLOCK>
-static hipError_t bwd(const StripArgs &a, hipStream_t s)
+template <int BLOCK, int KR, int KL, int MINB>
+static hipError_t bwd(const StripArgs &a, hipStream_t s, int *occ)
 {
+    if (occ) return query_occupancy((const void *)backward_kernel<BLOCK, KR, KL, MINB>, BLOCK, occ);
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
-    hipLaunchKernelGGL((backward_kernel<BLOCK, kr_bwd(BLOCK), kl_bwd(BLOCK)>), grid, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_backward_f32(const StripArgs &a, int block, float *grad_sigma, double inv_sigma, int nred,
-                               hipStream_t s)
+template <int BLOCK>
+static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
+    constexpr int KR = kr_bwd(BLOCK), KL = kl_bwd(BLOCK);
+    if (kc == KR) return bwd<BLOCK, KR, KL, 0>(a, s, occ);
+    // the half pass of 256 lanes fits three workgroups per compute unit
+    return bwd<BLOCK, KR / 2, (KL < KR / 2 ? KL : KR / 2), BLOCK == 256 ? 3 : 0>(a, s, occ);
+}
+
+hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
+                               int nred, hipStream_t s, int *occ)
+{
+    if (!valid_chunk_backward_f32(block, kc)) return hipErrorInvalidValue;
     hipError_t e;
     switch (block) {
-    case 256: e = bwd<256>(a, s); break;
-    case 512: e = bwd<512>(a, s); break;
-    case 1024: e = bwd<1024>(a, s); break;
+    case 256: e = bwd_block<256>(a, kc, s, occ); break;
+    case 512: e = bwd_block<512>(a, kc, s, occ); break;
+    case 1024: e = bwd_block<1024>(a, kc, s, occ); break;
     default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || occ) return e;
     if (grad_sigma) {
         hipLaunchKernelGGL(sigma_reduce_kernel, dim3(1), dim3(256), 0, s, nullptr, (const double *)a.red, nred,
                            inv_sigma, grad_sigma);
