@@ -6,8 +6,9 @@ nor links anything here, and nothing here imports the product package.
 
 The C source (``bsk_oracle.c``) evaluates eq. (3) of the paper directly with a
 box spatial window and the rescaled raised-cosine range kernel of eq. (6),
-cos^N(t / (sigma_r sqrt N)); see its header for the definitions.  This module
-only marshals NumPy arrays.
+cos^N(t / (sigma_r sqrt N)); the ``*_sp`` entry points add the separable
+raised-cosine spatial kernel of Algorithms 1 and 2 with M > 1.  See its header
+for the definitions.  This module only marshals NumPy arrays.
 """
 from __future__ import annotations
 
@@ -67,6 +68,18 @@ def _load():
     lib.oracle_bilateral_grad_f64.restype = None
     lib.oracle_bilateral_grad_f64.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                               ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_spatial_weight.restype = ctypes.c_double
+    lib.oracle_spatial_weight.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_bilateral_sp_f64.restype = None
+    lib.oracle_bilateral_sp_f64.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_bilateral_sp.restype = None
+    lib.oracle_bilateral_sp.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_bilateral_sp_at.restype = None
+    lib.oracle_bilateral_sp_at.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_int, _llp, ctypes.c_longlong,
+                                           _dp, _dp, _dp]
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -150,3 +163,36 @@ def bilateral_grad(f, gbar, radius: int, sigma_r: float, N: int):
     _load().oracle_bilateral_grad_f64(_ptr(f, _dp), _ptr(gbar, _dp), H, W, int(radius), float(sigma_r),
                                       int(N), _ptr(gf, _dp), ctypes.byref(gs), _ptr(u, _dp))
     return gf, gs.value, u
+
+
+def spatial_weight(d: float, sigma_s: float, Ns: int) -> float:
+    """One-dimensional spatial weight cos^Ns(d / (sigma_s sqrt Ns)); 1 for Ns = 0."""
+    return _load().oracle_spatial_weight(float(d), float(sigma_s), int(Ns))
+
+
+def bilateral_sp(f, radius: int, sigma_r: float, N: int, sigma_s: float, Ns: int, return_pq: bool = False):
+    """Whole image with the separable spatial kernel w(dy) w(dx); N = 0 is Algorithm 1."""
+    f = np.ascontiguousarray(f)
+    H, W = f.shape
+    out = np.empty((H, W), np.float64)
+    P = np.empty((H, W), np.float64) if return_pq else None
+    Q = np.empty((H, W), np.float64) if return_pq else None
+    if f.dtype == np.float64:
+        _load().oracle_bilateral_sp_f64(_ptr(f, _dp), H, W, int(radius), float(sigma_r), int(N), float(sigma_s),
+                                        int(Ns), _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    else:
+        f32 = np.ascontiguousarray(f, dtype=np.float32)
+        _load().oracle_bilateral_sp(_ptr(f32, _fp), H, W, int(radius), float(sigma_r), int(N), float(sigma_s),
+                                    int(Ns), _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    return (out, P, Q) if return_pq else out
+
+
+def bilateral_sp_at(f, idx, radius: int, sigma_r: float, N: int, sigma_s: float, Ns: int):
+    """The spatial-kernel filter at the flat (row-major) pixel indices ``idx`` only."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    H, W = f.shape
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size, np.float64)
+    _load().oracle_bilateral_sp_at(_ptr(f, _fp), H, W, int(radius), float(sigma_r), int(N), float(sigma_s),
+                                   int(Ns), _ptr(idx, _llp), idx.size, _ptr(out, _dp), None, None)
+    return out

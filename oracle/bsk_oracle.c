@@ -36,6 +36,9 @@
  * The gradient routine differentiates the same definition by hand (chain
  * rule through P, Q and the kernel), again by direct window sums.
  *
+ * The *_sp functions add the separable raised-cosine spatial kernel of
+ * Algorithms 1 and 2 with M > 1 (defined with oracle_spatial_weight below).
+ *
  * Conventions: images are row-major, H rows by W columns; float inputs are
  * widened exactly to double; accumulation is sequential in row-major window
  * order; rows are distributed over OpenMP threads.
@@ -360,6 +363,122 @@ void oracle_bilateral_grad_f64(const double *f, const double *gbar, int H, int W
     free(a);
     free(s1);
     free(rowsum);
+    kern_free(&k);
+}
+
+/*
+ * Spatial kernel of Algorithms 1 and 2 with M > 1 (Section 2, eq. (2) and
+ * eq. (3) with a non-trivial spatial kernel; Section 3, separable kernels):
+ * the product w(y_1 - x_1) w(y_2 - x_2) of one-dimensional raised cosines
+ *     w(d) = [cos(d / (sigma_s sqrt(Ns)))]^Ns,
+ * i.e. q_Ns of Section 3 in the scaling of eq. (6), whose Gaussian limit has
+ * standard deviation sigma_s (eq. (7) for the separable product).  Ns = 0
+ * gives w = 1, the box of the functions above.  The window B(x) is the same
+ * truncated (2r+1)^2 square.
+ */
+double oracle_spatial_weight(double d, double sigma_s, int Ns)
+{
+    if (Ns == 0) return 1.0;
+    double a = d / (sigma_s * sqrt((double)Ns));
+    return ipow(cos(a), Ns);
+}
+
+/* P, Q at one pixel with the spatial weights ws[d + r], d = -r .. r. */
+static void window_pq_sp(const double *f, long H, long W, long r, const kern_t *k, const double *ws,
+                         long i, long j, double *P, double *Q)
+{
+    double fx = f[i * W + j];
+    double p = 0.0, q = 0.0;
+    long y0 = lmax(0, i - r), y1 = lmin(H - 1, i + r);
+    long x0 = lmax(0, j - r), x1 = lmin(W - 1, j + r);
+    for (long y = y0; y <= y1; ++y) {
+        const double *row = f + y * W;
+        double wy = ws[y - i + r];
+        for (long x = x0; x <= x1; ++x) {
+            double fy = row[x];
+            double kv = wy * ws[x - j + r] * kern_eval(k, fy - fx);
+            p += kv * fy;
+            q += kv;
+        }
+    }
+    *P = p;
+    *Q = q;
+}
+
+static double *spatial_table(long r, double sigma_s, int Ns)
+{
+    double *ws = (double *)malloc(sizeof(double) * (size_t)(2 * r + 1));
+    for (long d = -r; d <= r; ++d) ws[d + r] = oracle_spatial_weight((double)d, sigma_s, Ns);
+    return ws;
+}
+
+/* Full image with the separable spatial kernel, double input; out, P, Q may
+ * be NULL independently.  N = 0 makes the range kernel 1: Algorithm 1, the
+ * normalised linear spatial filter. */
+void oracle_bilateral_sp_f64(const double *f, int H, int W, int radius, double sigma_r, int N,
+                             double sigma_s, int Ns, double *out, double *P, double *Q)
+{
+    kern_t k;
+    kern_init(&k, sigma_r, N, 0.0, 0);
+    long r = clamp_radius(radius, H, W);
+    double *ws = spatial_table(r, sigma_s, Ns);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < H; ++i) {
+        for (long j = 0; j < W; ++j) {
+            double p, q;
+            window_pq_sp(f, H, W, r, &k, ws, i, j, &p, &q);
+            if (out) out[i * W + j] = p / q;
+            if (P) P[i * W + j] = p;
+            if (Q) Q[i * W + j] = q;
+        }
+    }
+    free(ws);
+    kern_free(&k);
+}
+
+/* The same, float input (widened exactly). */
+void oracle_bilateral_sp(const float *f, int H, int W, int radius, double sigma_r, int N,
+                         double sigma_s, int Ns, double *out, double *P, double *Q)
+{
+    double *d = widen(f, (long)H * W);
+    oracle_bilateral_sp_f64(d, H, W, radius, sigma_r, N, sigma_s, Ns, out, P, Q);
+    free(d);
+}
+
+/* The same at selected pixels (flat row-major indices). */
+void oracle_bilateral_sp_at(const float *f, int H, int W, int radius, double sigma_r, int N,
+                            double sigma_s, int Ns, const long long *idx, long long n,
+                            double *out, double *P, double *Q)
+{
+    kern_t k;
+    kern_init(&k, sigma_r, N, 0.0, 0);
+    long r = clamp_radius(radius, H, W);
+    double *ws = spatial_table(r, sigma_s, Ns);
+#pragma omp parallel
+    {
+#pragma omp for schedule(dynamic, 64)
+        for (long long s = 0; s < n; ++s) {
+            long i = (long)(idx[s] / W), j = (long)(idx[s] % W);
+            double fx = (double)f[i * (long)W + j];
+            double p = 0.0, q = 0.0;
+            long y0 = lmax(0, i - r), y1 = lmin(H - 1, i + r);
+            long x0 = lmax(0, j - r), x1 = lmin(W - 1, j + r);
+            for (long y = y0; y <= y1; ++y) {
+                const float *row = f + y * (long)W;
+                double wy = ws[y - i + r];
+                for (long x = x0; x <= x1; ++x) {
+                    double fy = (double)row[x];
+                    double kv = wy * ws[x - j + r] * kern_eval(&k, fy - fx);
+                    p += kv * fy;
+                    q += kv;
+                }
+            }
+            if (out) out[s] = p / q;
+            if (P) P[s] = p;
+            if (Q) Q[s] = q;
+        }
+    }
+    free(ws);
     kern_free(&k);
 }
 

@@ -344,3 +344,109 @@ def test_huge_radius_covers_whole_image(oracle):
     for x in (0, 17, 53):
         k = np.array([_binom_kernel(fy - ff[x], 30.0, 30) for fy in ff])
         assert abs(a.ravel()[x] - (k * ff).sum() / k.sum()) < 1e-10
+
+
+# ---------------------------------------------------------------- P13 --------
+# The separable raised-cosine spatial kernel of Algorithms 1 and 2 with M > 1.
+def _binom_spatial(d, sigma_s, Ns):
+    """w(d) = cos^Ns(d / (sigma_s sqrt Ns)) as the exact binomial sum of cosines: order of
+    shiftability Ns + 1 per axis (Section 3), M = (Ns + 1)^2 in two dimensions."""
+    return _binom_kernel(d, sigma_s, Ns)
+
+
+@pytest.mark.parametrize("Ns", [0, 1, 2, 3, 4, 9])
+def test_spatial_weight_matches_binomial_expansion(oracle, Ns):
+    for d in range(-12, 13):
+        assert abs(oracle.spatial_weight(d, 3.0, Ns) - _binom_spatial(d, 3.0, Ns)) <= 1e-14
+
+
+def test_spatial_weight_gaussian_limit(oracle):
+    """Eq. (6) applied to the spatial kernel: w_Ns(d) -> exp(-d^2 / (2 sigma_s^2)) with the
+    error decaying like 1/Ns (the same constant 4/(3e^2) as the range kernel)."""
+    sigma_s = 2.5
+    for Ns in (400, 1600):
+        d = np.linspace(-4 * sigma_s, 4 * sigma_s, 801)
+        w = np.array([oracle.spatial_weight(x, sigma_s, Ns) for x in d])
+        sup = np.max(np.abs(w - np.exp(-d * d / (2 * sigma_s ** 2))))
+        assert abs(Ns * sup - 4 / (3 * math.e ** 2)) < 0.02 * 4 / (3 * math.e ** 2)
+
+
+def test_spatial_order_zero_is_the_box(oracle):
+    """Ns = 0 makes every spatial weight 1: the *_sp entry points equal the box ones."""
+    f = wl.random_image(19, 23, 31)
+    for r, N in ((0, 30), (2, 30), (4, 0), (30, 7)):
+        assert np.array_equal(oracle.bilateral_sp(f, r, 30.0, N, 2.0, 0), oracle.bilateral(f, r, 30.0, N))
+
+
+@pytest.mark.parametrize("r,sigma_s,Ns", [(1, 1.0, 1), (3, 2.0, 2), (5, 2.25, 2), (6, 3.0, 4), (9, 2.0, 7)])
+def test_algorithm1_is_normalised_separable_correlation(oracle, r, sigma_s, Ns):
+    """N = 0 (range kernel 1) is Algorithm 1: the normalised linear filter
+    sum_y w(y-x) f(y) / sum_y w(y-x) over the truncated window.  With zero padding this is
+    a separable correlation of f and of the indicator of the image, done here with
+    scipy.ndimage along each axis."""
+    from scipy import ndimage
+    f = wl.random_image(37, 41, 40 + r).astype(np.float64)
+    k1 = np.array([_binom_spatial(d, sigma_s, Ns) for d in range(-r, r + 1)])
+    def sep(a):
+        a = ndimage.correlate1d(a, k1, axis=0, mode="constant", cval=0.0)
+        return ndimage.correlate1d(a, k1, axis=1, mode="constant", cval=0.0)
+    ref = sep(f) / sep(np.ones_like(f))
+    out = oracle.bilateral_sp(f, r, 30.0, 0, sigma_s, Ns)
+    assert np.max(np.abs(out - ref)) <= 1e-11 * T
+
+
+def _brute_sp(f, r, sigma, N, sigma_s, Ns):
+    """Pure-Python Algorithm 2 definition with the spatial weights and the range kernel both
+    taken as exact binomial sums of cosines."""
+    H, W = f.shape
+    P = np.empty((H, W))
+    Q = np.empty((H, W))
+    ws = {d: _binom_spatial(d, sigma_s, Ns) for d in range(-r, r + 1)}
+    for i in range(H):
+        for j in range(W):
+            fx = float(f[i, j])
+            ps, qs = [], []
+            for y in range(max(0, i - r), min(H - 1, i + r) + 1):
+                for x in range(max(0, j - r), min(W - 1, j + r) + 1):
+                    fy = float(f[y, x])
+                    k = ws[y - i] * ws[x - j] * _binom_kernel(fy - fx, sigma, N)
+                    ps.append(k * fy)
+                    qs.append(k)
+            P[i, j] = math.fsum(ps)
+            Q[i, j] = math.fsum(qs)
+    return P, Q
+
+
+@pytest.mark.parametrize("r,N,sigma_s,Ns,shape", [(1, 4, 1.0, 1, (7, 9)), (2, 30, 2.0, 2, (11, 8)),
+                                                   (4, 5, 2.5, 3, (9, 12)), (3, 117, 1.5, 4, (6, 10))])
+def test_spatial_brute_force_small(oracle, r, N, sigma_s, Ns, shape):
+    f = wl.random_image(*shape, seed=70 + r)
+    sig = 30.0 if N >= 30 else 200.0
+    Pr, Qr = _brute_sp(f, r, sig, N, sigma_s, Ns)
+    out, P, Q = oracle.bilateral_sp(f, r, sig, N, sigma_s, Ns, return_pq=True)
+    nwin = (2 * r + 1) ** 2
+    assert np.max(np.abs(P - Pr)) <= 1e-13 * nwin * T
+    assert np.max(np.abs(Q - Qr)) <= 1e-13 * nwin
+    ok = np.abs(Qr) > 0.1
+    assert np.max(np.abs(out - Pr / Qr)[ok]) <= 1e-12 * T
+
+
+def test_spatial_filter_invariants(oracle):
+    """Constant images are fixed; transposing or flipping the image transposes or flips
+    the result (the spatial kernel is separable, symmetric and the same on both axes);
+    adding a constant shifts the result (the range kernel sees differences only)."""
+    f = wl.random_image(14, 19, 77)
+    a = oracle.bilateral_sp(f, 3, 30.0, 30, 2.0, 2)
+    assert np.max(np.abs(oracle.bilateral_sp(np.full((9, 8), 99.0), 3, 30.0, 30, 2.0, 2) - 99.0)) < 1e-12
+    assert np.max(np.abs(oracle.bilateral_sp(np.ascontiguousarray(f.T), 3, 30.0, 30, 2.0, 2) - a.T)) < 1e-11
+    assert np.max(np.abs(oracle.bilateral_sp(np.ascontiguousarray(f[::-1, ::-1]), 3, 30.0, 30, 2.0, 2)
+                         - a[::-1, ::-1])) < 1e-11
+    b = oracle.bilateral_sp(f.astype(np.float64) + 17.0, 3, 30.0, 30, 2.0, 2)
+    assert np.max(np.abs(b - (a + 17.0))) < 1e-10
+
+
+def test_spatial_sampled_matches_full(oracle):
+    f = wl.rect_image(30, 40, seed=2)
+    full = oracle.bilateral_sp(f, 5, 30.0, 30, 2.25, 2)
+    idx = np.array([0, 7, 39, 40, 1199, 345, 777])
+    assert np.array_equal(oracle.bilateral_sp_at(f, idx, 5, 30.0, 30, 2.25, 2), full.ravel()[idx])
