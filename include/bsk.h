@@ -82,6 +82,17 @@ typedef struct {
     int strip_h;          /* output rows per workgroup; 0 = auto */
     int order_chunk;      /* FP32 forward: orders per pass, the full or the half pass of the
                              block (256: 16|8, 512: 8|4, 1024: 4|2); 0 = auto */
+    /* Spatial kernel (Algorithms 1 and 2 with M > 1; Section 3, separable
+     * kernels): 0 = the box; Ns in 1..6 = the separable raised cosine
+     * w(dy) w(dx), w(d) = cos^Ns(d / (spatial_sigma sqrt Ns)) on the same
+     * (2r+1)^2 window (spatial basis of M = (Ns+1)^2 functions); -1 = the
+     * smallest Ns keeping w non-negative and unimodal on [-r, r],
+     * ceil((2r / (pi spatial_sigma))^2), which must not exceed 6.  The
+     * paper's q_Ns(t) = cos^Ns(pi t / 2T_s) is spatial_sigma = 2 T_s / (pi sqrt Ns).
+     * Supported by the plain FP32 forward (bilateral_shiftable_ex) with
+     * 256- or 512-lane strips; the other entry points return BSK_EUNSUPPORTED. */
+    int spatial_N;
+    double spatial_sigma; /* > 0 when spatial_N != 0 */
 } bsk_options;
 
 /*

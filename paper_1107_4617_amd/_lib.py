@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
     _fields_ = [("order_mode", ctypes.c_int), ("N", ctypes.c_int), ("precision", ctypes.c_int),
                 ("weight_eps", ctypes.c_double), ("kahan", ctypes.c_int), ("pitch_in", ctypes.c_int),
                 ("pitch_out", ctypes.c_int), ("block", ctypes.c_int), ("strip_h", ctypes.c_int),
-                ("order_chunk", ctypes.c_int)]
+                ("order_chunk", ctypes.c_int), ("spatial_N", ctypes.c_int), ("spatial_sigma", ctypes.c_double)]
 
 
 class ImageDesc(ctypes.Structure):

@@ -1,4 +1,5 @@
 // C ABI of libbsk: argument validation, planning, workspace and launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -112,8 +113,8 @@ static int pick_chunk(int K, int full)
 static int kernel_occupancy(const Resolved &r, int kind)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, int>, int> cache;
-    const auto key = std::make_tuple(kind, r.block, r.kc, r.prec, r.kahan, [] {
+    static std::map<std::tuple<int, int, int, int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(kind, r.block, r.kc, r.prec, r.kahan, r.sp.nsc * 2 + (r.sp.even ? 1 : 0), [] {
         int d = 0;
         (void)hipGetDevice(&d);
         return d;
@@ -126,7 +127,9 @@ static int kernel_occupancy(const Resolved &r, int kind)
     bsk::StripArgs a;
     std::memset(&a, 0, sizeof(a));
     int occ = 1;
-    if (kind == kTrain) {
+    if (r.sp.Ns > 0) {
+        (void)bsk::launch_spatial_f32(a, r.block, r.sp, nullptr, &occ);
+    } else if (kind == kTrain) {
         (void)bsk::launch_train_f32(a, r.block, nullptr, &occ);
     } else if (kind == kBackward) {
         (void)bsk::launch_backward_f32(a, r.block, r.kc, nullptr, 0.0, 0, nullptr, &occ);
@@ -175,15 +178,36 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         return fail(BSK_ERANGE, "order N=%d leaves more than %d folded orders (raise weight_eps)", r->N,
                     bsk::kMaxOrders);
 
-    // Clamping the radius to the image leaves every truncated window unchanged.
+    // Clamping the radius to the image leaves every truncated window unchanged
+    // (offsets beyond the image never occur, so no spatial weight changes).
     r->rh = radius < W - 1 ? radius : W - 1;
     r->rv = radius < H - 1 ? radius : H - 1;
     if (r->rh > BSK_MAX_RADIUS)
         return fail(BSK_EUNSUPPORTED, "clamped radius %d exceeds %d", r->rh, BSK_MAX_RADIUS);
 
+    // spatial kernel: order Ns (or N_0 for the window), its folded plan
+    r->sp = bsk::SpatialPlan();
+    if (o.spatial_N < -1) return fail(BSK_EINVAL, "spatial_N must be >= -1");
+    if (o.spatial_N != 0) {
+        if (!finite_pos(o.spatial_sigma)) return fail(BSK_EINVAL, "spatial_sigma must be finite and > 0");
+        int Ns = o.spatial_N;
+        if (Ns < 0) {
+            const double x = 2.0 * (double)radius / (M_PI * o.spatial_sigma);
+            if (!(x * x < 1e6)) return fail(BSK_ERANGE, "automatic spatial order too large");
+            Ns = std::max(1, (int)std::ceil(x * x));
+        }
+        if (Ns > 2 * bsk::kMaxSpatialFreq)
+            return fail(BSK_ERANGE, "spatial order %d exceeds %d (raise spatial_sigma)", Ns, 2 * bsk::kMaxSpatialFreq);
+        if (bsk::make_spatial_plan(Ns, o.spatial_sigma, &r->sp) != 0)
+            return fail(BSK_EINVAL, "bad spatial kernel");
+        if (kind != kForward || r->prec != BSK_FP32 || r->kahan)
+            return fail(BSK_EUNSUPPORTED, "the spatial kernel runs in the plain FP32 forward only");
+    }
+    const bool spatial = r->sp.Ns > 0;
+
     int block = o.block;
     int tuned_S = 0, tuned_kc = 0;
-    if (kind == kForward && o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
+    if (kind == kForward && !spatial && o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
         int tb = 0, ts = 0, tk = 0;
         if (tuned_shape(r->rh, r->plan.K, H, W, r->prec, &tb, &ts, &tk)) {
             block = tb;
@@ -203,12 +227,22 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     }
     if (block != 256 && block != 512 && block != 1024)
         return fail(BSK_EINVAL, "block must be 256, 512 or 1024");
+    if (spatial && !bsk::spatial_block_ok(block, r->sp.nsc)) {
+        if (o.block || !bsk::spatial_block_ok(512, r->sp.nsc) || 512 - 2 * r->rh < 1)
+            return fail(BSK_EUNSUPPORTED, "spatial order %d with radius %d: no strip shape (256 lanes, or 512 "
+                        "for orders up to 4)", r->sp.Ns, r->rh);
+        block = 512;
+    }
     if (block - 2 * r->rh < 1)
         return fail(BSK_EUNSUPPORTED, "radius %d too large for a %d-lane strip", r->rh, block);
     r->block = block;
     if (o.order_chunk < 0) return fail(BSK_EINVAL, "order_chunk must be >= 0");
     int kc = o.order_chunk ? o.order_chunk : tuned_kc;
-    if (kind == kTrain) {
+    if (spatial) {
+        kc = bsk::chunk_spatial_f32(block, r->sp.nsc);
+        if (o.order_chunk && o.order_chunk != kc)
+            return fail(BSK_EINVAL, "order_chunk %d is not the spatial kernel's pass size %d", o.order_chunk, kc);
+    } else if (kind == kTrain) {
         kc = bsk::chunk_train_f32(block);
     } else if (kind == kBackward) {
         if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_backward_f32(block));
@@ -309,6 +343,24 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
         st = get_ws(stream, 0, (size_t)bsk::acc_count_forward() * H * W * esz, &ws);
         if (st) return st;
         a.ws = ws;
+    }
+    if (r.sp.Ns > 0) {
+        // phase tables (cos, sin)(nu_j y) for the rows and columns, then the kernel
+        void *tab = nullptr;
+        const size_t nrow = (size_t)H * r.sp.nsc * 2, ncol = (size_t)W * r.sp.nsc * 2;
+        st = get_ws(stream, 5, (nrow + ncol) * sizeof(float), &tab);
+        if (st) return st;
+        float *rowtab = (float *)tab, *coltab = rowtab + nrow;
+        hipError_t e = bsk::launch_phase_table(r.sp, H, rowtab, (hipStream_t)stream);
+        if (e == hipSuccess) e = bsk::launch_phase_table(r.sp, W, coltab, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "phase table launch");
+        a.sp_u0 = (float)r.sp.u0;
+        for (int j = 0; j < bsk::kMaxSpatialFreq; ++j) a.sp_u[j] = (float)r.sp.u[j];
+        a.sp_row = rowtab;
+        a.sp_col = coltab;
+        e = bsk::launch_spatial_f32(a, r.block, r.sp, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "spatial forward launch");
+        return BSK_OK;
     }
     hipError_t e = r.prec == BSK_FP64
                        ? bsk::launch_forward_f64(a, r.block, (hipStream_t)stream)

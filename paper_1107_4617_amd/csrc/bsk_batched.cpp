@@ -37,6 +37,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     std::memset(&o, 0, sizeof(o));
     if (opt) o = *opt;
     if (o.precision != BSK_FP32 || o.kahan) return fail(BSK_EUNSUPPORTED, "the batched path is FP32");
+    if (o.spatial_N != 0) return fail(BSK_EUNSUPPORTED, "the batched path uses the box spatial kernel");
     if (o.pitch_in || o.pitch_out) return fail(BSK_EUNSUPPORTED, "the batched path needs dense pitch");
     if (o.strip_h < 0 || !(o.weight_eps >= 0.0)) return fail(BSK_EINVAL, "bad options");
 
@@ -468,6 +469,7 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     o.block = 0;
     o.strip_h = 0;
     o.order_chunk = 0;
+    if (o.spatial_N != 0) return fail(BSK_EUNSUPPORTED, "the autotuner covers the box spatial kernel");
     Resolved base;
     int st = resolve(H, W, radius, sigma_r, T, &o, &base);
     if (st) return st;

@@ -68,6 +68,9 @@ __global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const
         gm.v = a.vtab + im.v_off;
         gm.vf = a.vtabf + im.v_off;
         gm.ws = im.ws_off >= 0 ? (void *)(a.ws + im.ws_off) : nullptr;
+        gm.sp_u0 = 1.0f;   // the box spatial kernel
+        for (int j = 0; j < kMaxSpatialFreq; ++j) gm.sp_u[j] = 0.0f;
+        gm.sp_row = gm.sp_col = nullptr;
         strip_body<float, BLOCK, KC, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
                                                                                     nullptr, nullptr);
         __syncthreads();

@@ -12,34 +12,33 @@
 // Mapping onto the GPU.  A workgroup owns a strip of BLOCK image columns (its
 // Wt = BLOCK - 2 rh output columns plus rh halo columns on each side) and a
 // segment of S output rows, which it walks from top to bottom.  Lane t owns
-// column j0 - rh + t.  Per output row i:
-//   phase V  every lane updates, in registers, the vertical moving sums of all
-//            channels of its column for the pass's KC orders:
-//            V += X(i + rv) - X(i - rv - 1).  The transforms X come from a
-//            rotation recurrence over the orders (one sincos pair per pixel,
-//            then a 2x2 rotation per order), so cos/sin are never evaluated
-//            per order.  V is written to an LDS row buffer.
-//   phase H  "walker" lanes turn each LDS row into its prefix sums in place:
-//            each walker scans a chunk of the row in registers and the
-//            chunk totals are combined by a scan across the row's walkers.
-//   phase R  every output lane forms the horizontal box sums as prefix
-//            differences B(j) = P(j + rh) - P(j - rh - 1) and recombines its
-//            pixel from the box sums of all orders and the transforms of its
-//            own value (kept in registers).
-// The (channels x orders) stack therefore lives only in registers and LDS; HBM
-// sees the input (read ~3 times through L2: as incoming, centre and outgoing
-// row, each load issued one row ahead) and the output.  Values are centred on
-// a per-workgroup reference level before transforming (the filter is shift
-// covariant), which halves the magnitude of the f-weighted sums.  The order
-// count is padded to a multiple of KC with zero weights, so every pass runs
-// the same straight-line code; passes after the first continue from partial
-// accumulators kept in a workspace.
+// column j0 - rh + t.  Per output row i, for each group of KL orders:
+//   stage V  every lane updates, in registers, the vertical moving sums of all
+//            channels of its column: V += X(i + rv) - X(i - rv - 1).  The
+//            transforms X come from a three-term recurrence over the orders
+//            (one sincos per pixel), so cos/sin are never evaluated per order.
+//            V is written to an LDS row buffer.
+//   stage H  "walker" lanes turn each LDS row into its exclusive prefix sums
+//            E in place: each walker scans a chunk of the row in registers and
+//            the chunk totals are combined by a scan across the row's walkers.
+//   stage R  every output lane forms the horizontal box sums as prefix
+//            differences B(j) = E(j + rh + 1) - E(j - rh) and recombines its
+//            pixel from the box sums and the transforms of its own value.
+// The three stages are software-pipelined over three row buffers (see
+// strip_body).  The (channels x orders) stack therefore lives only in
+// registers and LDS; HBM sees the input (read ~3 times through L2: as
+// incoming, centre and outgoing row, each load issued one row ahead) and the
+// output.  Values are centred on a per-workgroup reference level before
+// transforming (the filter is shift covariant), which halves the magnitude of
+// the f-weighted sums.  The order count is padded to a multiple of the pass
+// size with zero weights, so every pass runs the same straight-line code;
+// passes after the first continue from partial accumulators kept in a
+// workspace.
 #pragma once
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
-
 
 #include "bsk_internal.h"
 
@@ -359,6 +358,13 @@ struct Geom {
     const double *v;   // folded weights (FP64), K entries, zero past the kept orders
     const float *vf;   // the same weights in FP32
     void *ws;          // NACC planes of H*W accumulators, or null when K <= KC
+    // separable spatial kernel (Algorithms 1 and 2 with M > 1): weight of the
+    // zero frequency and of each spatial frequency, and the phase tables
+    // (cos, sin)(nu_j y) per row and (cos, sin)(nu_j x) per column
+    float sp_u0;
+    float sp_u[kMaxSpatialFreq];
+    const float *sp_row;
+    const float *sp_col;
 };
 
 template <typename AT>
@@ -398,11 +404,15 @@ constexpr int floormod(int a, int b) { return a - floordiv(a, b) * b; }
 // LDS row buffers of the pipeline: the V stage fills one while the H stage
 // scans the previous one and the R stage reads the one before that.
 constexpr int kNBuf = 3;
-template <int NCH, int KL, int BLOCK>
+// LDS rows per channel and order: 1 for the box; with the spatial kernel one
+// row per horizontal basis function (the zero frequency when Ns is even, and
+// a cosine and a sine row per non-zero frequency).
+constexpr int spatial_rows(int nsc, bool even) { return nsc == 0 ? 1 : (even ? 1 : 0) + 2 * nsc; }
+template <int NCH, int KL, int BLOCK, int NSC = 0, bool SEVEN = true>
 constexpr int strip_lds_elems()
 {
-    return kNBuf * NCH * KL *
-           row_stride(BLOCK, walker_count(BLOCK, NCH * KL), walker_chunk(BLOCK, walker_count(BLOCK, NCH * KL)));
+    constexpr int rows = NCH * KL * spatial_rows(NSC, SEVEN);
+    return kNBuf * rows * row_stride(BLOCK, walker_count(BLOCK, rows), walker_chunk(BLOCK, walker_count(BLOCK, rows)));
 }
 
 // Exclusive prefix sums over aligned groups of CH consecutive lanes (CH a power
@@ -444,7 +454,19 @@ __device__ __forceinline__ AT group_exclusive_scan(AT x, int wch)
 // interval mixes the VALU-heavy V stage with the LDS-heavy H and R stages.
 // KR orders are carried in registers per pass (the vertical sums of all their
 // channels), NSUB = KR / KL intervals per row.
-template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN>
+//
+// With NSC > 0 the spatial kernel is the separable raised cosine
+// w(dy) w(dx), w(d) = u0 + sum_j u_j cos(nu_j d) (u0 = 0 unless SEVEN), rather
+// than the box.  The vertical factor is exact in the V stage: next to the plain
+// moving sum V, each channel keeps per frequency the running sum
+// W_j = sum_{y in window} e^{i nu_j y} X(y) (absolute rows, so the update needs
+// no rotation), and the row written to LDS is the weighted vertical sum
+// VQ(i) = u0 V + sum_j Re(e^{-i nu_j i} W_j).  The horizontal factor uses the
+// shift identity along the row: VQ, VQ cos(nu_j x) and VQ sin(nu_j x) are
+// prefix-summed, and the R stage forms
+// u0 Box[VQ] + sum_j u_j (cos(nu_j x) Box[VQ cos] + sin(nu_j x) Box[VQ sin]).
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int NSC = 0,
+          bool SEVEN = true>
 __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, int by, AT *lds,
                                            double *red_lds, double *red_out)
 {
@@ -453,7 +475,10 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     constexpr int NAUX = POL::NAUX;
     constexpr int NRAW = POL::NRAW;
     constexpr int NPAIR = POL::NPAIR;
-    constexpr int ROWS = NCH * KL;
+    constexpr int NB = spatial_rows(NSC, SEVEN);
+    constexpr bool PLAIN = NSC == 0 || SEVEN;   // the zero spatial frequency is present
+    constexpr int NSCR = NSC > 0 ? NSC : 1;      // array extent
+    constexpr int ROWS = NCH * KL * NB;
     constexpr int CH = walker_count(BLOCK, ROWS);
     constexpr int G = walker_chunk(BLOCK, CH);
     constexpr int RS = row_stride(BLOCK, CH, G);
@@ -462,6 +487,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     static_assert(NCH == 2 * NPAIR, "channels come in (cos, sin) pairs");
     static_assert(KR % KL == 0, "KR must be a multiple of KL");
     static_assert(CH * G >= BLOCK + 1 && RS >= CH * G && ROWS * CH <= BLOCK, "walker geometry");
+    static_assert(NSC <= kMaxSpatialFreq && (NSC == 0 || (!KAHAN && sizeof(AT) == 4)),
+                  "the spatial kernel runs the plain FP32 forward");
 
     const int t = threadIdx.x;
     const int H = gm.H, W = gm.W, rh = gm.rh, rv = gm.rv;
@@ -493,6 +520,26 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     const int phi = t + rh + 1;
     const int plo = t - rh;
 
+    // spatial kernel: this column's horizontal basis values (V stage) and the
+    // output column's coefficients u_j (cos, sin)(nu_j x) (R stage)
+    float hc[NSCR], hs[NSCR], rcw[NSCR], rsw[NSCR];
+    const float u0 = NSC > 0 ? gm.sp_u0 : 1.0f;
+#pragma unroll
+    for (int j = 0; j < NSCR; ++j) {
+        hc[j] = hs[j] = rcw[j] = rsw[j] = 0.0f;
+        if constexpr (NSC > 0) {
+            hc[j] = gm.sp_col[2 * ((long)j * W + jxc)];
+            hs[j] = gm.sp_col[2 * ((long)j * W + jxc) + 1];
+            rcw[j] = gm.sp_u[j] * hc[j];
+            rsw[j] = gm.sp_u[j] * hs[j];
+        }
+    }
+    // (cos, sin)(nu_j y) of image row y, uniform over the workgroup
+    auto phase = [&](int j, int y, float *c, float *s) {
+        *c = gm.sp_row[2 * ((long)j * H + y)];
+        *s = gm.sp_row[2 * ((long)j * H + y) + 1];
+    };
+
     double red = 0.0;
 
     for (int m0 = 0; m0 < gm.K; m0 += KR) {
@@ -504,12 +551,15 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
 
         AT V[KR][NCH];
         AT Cmp[KAHAN ? KR : 1][NCH];
+        AT Wr[NSC > 0 ? KR : 1][NCH][NSCR], Wi[NSC > 0 ? KR : 1][NCH][NSCR];
 #pragma unroll
         for (int m = 0; m < KR; ++m)
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 V[m][ch] = AT(0);
                 Cmp[KAHAN ? m : 0][ch] = AT(0);
+#pragma unroll
+                for (int j = 0; j < NSCR; ++j) Wr[NSC > 0 ? m : 0][ch][j] = Wi[NSC > 0 ? m : 0][ch][j] = AT(0);
             }
 
         // initial window: rows [i0 - rv, i0 + rv - 1] (the first step adds i0 + rv)
@@ -521,6 +571,19 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 POL::template make<AT>(raw, ref, aux);
                 POL::template kappa<AT>(aux, kp);
                 POL::template fetch<AT>(a, colok, rowc(y + 1), jxc, raw);
+                AT kc[NPAIR][NSCR], ks[NPAIR][NSCR];
+                if constexpr (NSC > 0) {
+#pragma unroll
+                    for (int j = 0; j < NSC; ++j) {
+                        float c, s;
+                        phase(j, y, &c, &s);
+#pragma unroll
+                        for (int p = 0; p < NPAIR; ++p) {
+                            kc[p][j] = kp[p] * c;
+                            ks[p][j] = kp[p] * s;
+                        }
+                    }
+                }
                 Chain<AT> ch;
                 ch.start(colok, aux[0], om0, dlt, smode);
 #pragma unroll
@@ -528,8 +591,19 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     const AT C = quant<QUANT>(ch.c), S = quant<QUANT>(ch.s);
 #pragma unroll
                     for (int p = 0; p < NPAIR; ++p) {
-                        V[m][2 * p] = fmat(kp[p], C, V[m][2 * p]);
-                        V[m][2 * p + 1] = fmat(kp[p], S, V[m][2 * p + 1]);
+                        if constexpr (PLAIN) {
+                            V[m][2 * p] = fmat(kp[p], C, V[m][2 * p]);
+                            V[m][2 * p + 1] = fmat(kp[p], S, V[m][2 * p + 1]);
+                        }
+                        if constexpr (NSC > 0) {
+#pragma unroll
+                            for (int j = 0; j < NSC; ++j) {
+                                Wr[m][2 * p][j] = fmat(kc[p][j], C, Wr[m][2 * p][j]);
+                                Wi[m][2 * p][j] = fmat(ks[p][j], C, Wi[m][2 * p][j]);
+                                Wr[m][2 * p + 1][j] = fmat(kc[p][j], S, Wr[m][2 * p + 1][j]);
+                                Wi[m][2 * p + 1][j] = fmat(ks[p][j], S, Wi[m][2 * p + 1][j]);
+                            }
+                        }
                     }
                     ch.step();
                 }
@@ -547,6 +621,16 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
         }
         Chain<AT> ci, co, cc;
         AT ki[NPAIR], ko[NPAIR], auxc[NAUX], acc[NACC];
+        // spatial kernel: kappa times the phases of the incoming and outgoing
+        // rows, and u_j (cos, sin)(nu_j i) of the output row
+        AT kic[NPAIR][NSCR], kis[NPAIR][NSCR], koc[NPAIR][NSCR], kos[NPAIR][NSCR];
+        AT dc[NSCR], ds[NSCR];
+#pragma unroll
+        for (int j = 0; j < NSCR; ++j) {
+            dc[j] = ds[j] = AT(0);
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p) kic[p][j] = kis[p][j] = koc[p][j] = kos[p][j] = AT(0);
+        }
 #pragma unroll
         for (int p = 0; p < NPAIR; ++p) ki[p] = ko[p] = AT(0);
 #pragma unroll
@@ -591,8 +675,25 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         AT B[NCH];
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) {
-                            const AT *row = VbR + (k * NCH + c) * RS;
-                            B[c] = row[phi] - row[plo];
+                            const AT *row = VbR + (k * NCH + c) * NB * RS;
+                            if constexpr (NSC == 0) {
+                                B[c] = row[phi] - row[plo];
+                            } else {
+                                AT hq = AT(0);
+                                int b = 0;
+                                if constexpr (SEVEN) {
+                                    hq = u0 * (row[phi] - row[plo]);
+                                    b = 1;
+                                }
+#pragma unroll
+                                for (int j = 0; j < NSC; ++j) {
+                                    const AT *rc_ = row + (b + 2 * j) * RS;
+                                    const AT *rs_ = rc_ + RS;
+                                    hq = fmat(rcw[j], rc_[phi] - rc_[plo], hq);
+                                    hq = fmat(rsw[j], rs_[phi] - rs_[plo], hq);
+                                }
+                                B[c] = hq;
+                            }
                         }
                         const AT v = weight<AT>(gm, m0 + m);
                         const AT vom = v * (om0 + (AT)m * dlt);
@@ -637,6 +738,24 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         POL::template fetch<AT>(a, colok && yout + 1 >= ylo, rowc(yout + 1), jxc, rout);
                         ci.start(vin, auxi[0], om0, dlt, smode);
                         co.start(vout, auxo[0], om0, dlt, smode);
+                        if constexpr (NSC > 0) {
+#pragma unroll
+                            for (int j = 0; j < NSC; ++j) {
+                                float c1, s1, c2, s2, c3, s3;
+                                phase(j, rowc(yin), &c1, &s1);
+                                phase(j, rowc(yout), &c2, &s2);
+                                phase(j, i, &c3, &s3);
+                                dc[j] = gm.sp_u[j] * c3;
+                                ds[j] = gm.sp_u[j] * s3;
+#pragma unroll
+                                for (int p = 0; p < NPAIR; ++p) {
+                                    kic[p][j] = ki[p] * c1;
+                                    kis[p][j] = ki[p] * s1;
+                                    koc[p][j] = ko[p] * c2;
+                                    kos[p][j] = ko[p] * s2;
+                                }
+                            }
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < KL; ++k) {
@@ -656,12 +775,45 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                     V[m][c] = s;
                                 }
                             } else {
-                                V[m][2 * p] = fmat(-ko[p], Co, fmat(ki[p], Ci, V[m][2 * p]));
-                                V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
+                                if constexpr (PLAIN) {
+                                    V[m][2 * p] = fmat(-ko[p], Co, fmat(ki[p], Ci, V[m][2 * p]));
+                                    V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
+                                }
+                                if constexpr (NSC > 0) {
+#pragma unroll
+                                    for (int j = 0; j < NSC; ++j) {
+                                        AT *wr0 = &Wr[m][2 * p][j], *wi0 = &Wi[m][2 * p][j];
+                                        AT *wr1 = &Wr[m][2 * p + 1][j], *wi1 = &Wi[m][2 * p + 1][j];
+                                        *wr0 = fmat(-koc[p][j], Co, fmat(kic[p][j], Ci, *wr0));
+                                        *wi0 = fmat(-kos[p][j], Co, fmat(kis[p][j], Ci, *wi0));
+                                        *wr1 = fmat(-koc[p][j], So, fmat(kic[p][j], Si, *wr1));
+                                        *wi1 = fmat(-kos[p][j], So, fmat(kis[p][j], Si, *wi1));
+                                    }
+                                }
                             }
                         }
 #pragma unroll
-                        for (int c = 0; c < NCH; ++c) VbV[(k * NCH + c) * RS + vpos] = V[m][c];
+                        for (int c = 0; c < NCH; ++c) {
+                            AT *row = VbV + (k * NCH + c) * NB * RS + vpos;
+                            if constexpr (NSC == 0) {
+                                row[0] = V[m][c];
+                            } else {
+                                // vertically weighted sum, then its horizontal basis rows
+                                AT vq = PLAIN ? u0 * V[m][c] : AT(0);
+#pragma unroll
+                                for (int j = 0; j < NSC; ++j) vq = fmat(ds[j], Wi[m][c][j], fmat(dc[j], Wr[m][c][j], vq));
+                                int b = 0;
+                                if constexpr (SEVEN) {
+                                    row[0] = vq;
+                                    b = 1;
+                                }
+#pragma unroll
+                                for (int j = 0; j < NSC; ++j) {
+                                    row[(b + 2 * j) * RS] = vq * hc[j];
+                                    row[(b + 2 * j + 1) * RS] = vq * hs[j];
+                                }
+                            }
+                        }
                         ci.step();
                         co.step();
                     }

@@ -25,6 +25,7 @@ struct Resolved {
     int kc;        // orders per pass of the kernel the request runs
     int S;
     bsk::Plan plan;
+    bsk::SpatialPlan sp;   // Ns = 0: the box
 };
 
 // The kernel family a request is resolved for: its pass sizes and residency

@@ -8,6 +8,7 @@ namespace bsk {
 
 constexpr int kMaxOrders = 256;   // folded orders a plan may keep
 constexpr int kArgOrders = 272;   // weight slots in kernel arguments (kept orders padded to a pass)
+constexpr int kMaxSpatialFreq = 3; // non-zero frequencies of the spatial kernel (order Ns <= 6)
 
 // Folded plan of the raised-cosine range kernel (Section 3, q_N, eq. (6)).
 // The unfolded expansion cos^N(a) = 2^-N sum_n C(N,n) cos((2n-N) a) pairs
@@ -30,6 +31,23 @@ struct Plan {
 
 // Builds the plan; returns 0, or -2 if more than kMaxOrders orders remain.
 int make_plan(int N, double sigma_r, double eps, Plan *p);
+
+// Folded plan of the separable spatial kernel w(d) = cos^Ns(d / (sigma_s sqrt Ns))
+// (Section 3, q_Ns in the scaling of eq. (6)): w(d) = u0 + sum_j u[j] cos(nu[j] d),
+// with nu[j] = (Ns - 2j) / (sigma_s sqrt Ns) for j < nsc = ceil(Ns / 2),
+// u[j] = 2 * 2^-Ns C(Ns, j), and u0 = 2^-Ns C(Ns, Ns/2) when Ns is even (0 when
+// odd).  Ns = 0 is the box (nsc = 0, u0 = 1).
+struct SpatialPlan {
+    int Ns = 0;
+    int nsc = 0;
+    bool even = true;
+    double sigma = 0.0;
+    double u0 = 1.0;
+    double u[kMaxSpatialFreq] = {0.0, 0.0, 0.0};
+    double nu[kMaxSpatialFreq] = {0.0, 0.0, 0.0};
+};
+// Returns 0, or -1 if Ns is negative or above 2 kMaxSpatialFreq or sigma_s is not positive.
+int make_spatial_plan(int Ns, double sigma_s, SpatialPlan *sp);
 int order_for(double sigma_r, double T);
 // Full folded-order count and dropped mass without the kMaxOrders limit.
 void plan_counts(int N, double eps, int *K, double *dropped);
@@ -62,6 +80,11 @@ struct StripArgs {
     double omega_base, delta;
     double v[kArgOrders];  // folded weights, zero past the kept orders
     float vf[kArgOrders];  // the same in FP32
+    // separable spatial kernel (unused by the box kernels)
+    float sp_u0;
+    float sp_u[kMaxSpatialFreq];
+    const float *sp_row;   // (cos, sin)(nu_j y), j-major, H rows
+    const float *sp_col;   // (cos, sin)(nu_j x), j-major, W columns
 };
 
 // Launch helpers implemented in bsk_kernels.hip.  `prec` selects the stack
@@ -74,6 +97,14 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int 
 hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);
+// FP32 forward with the separable spatial kernel of plan sp (nsc >= 1).
+hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, hipStream_t s,
+                              int *occ = nullptr);
+// Fills tab[2 (j n + y) + {0, 1}] = (cos, sin)(nu[j] y) for y < n, j < sp.nsc, in FP64
+// with the angle reduced modulo 2 pi before rounding to FP32.
+hipError_t launch_phase_table(const SpatialPlan &sp, int n, float *tab, hipStream_t s);
+int chunk_spatial_f32(int block, int nsc);
+bool spatial_block_ok(int block, int nsc);
 
 // Orders per pass of the strip kernel for a kernel family/block; the FP32
 // forward and the adjoint offer a full and a half pass size per block.

@@ -35,11 +35,8 @@ constexpr int default_minb()
 
 // MINB: workgroups per compute unit the register allocation targets (0: the
 // LDS-derived default).
-template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
-__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, KL, BLOCK, AT>()))
-    strip_kernel(const StripArgs a)
+__device__ __forceinline__ Geom geom_of(const StripArgs &a)
 {
-    __shared__ AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
     Geom gm;
     gm.H = a.io.H;
     gm.W = a.io.W;
@@ -55,7 +52,51 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, K
     gm.v = a.v;
     gm.vf = a.vf;
     gm.ws = a.ws;
+    gm.sp_u0 = a.sp_u0;
+    for (int j = 0; j < kMaxSpatialFreq; ++j) gm.sp_u[j] = a.sp_u[j];
+    gm.sp_row = a.sp_row;
+    gm.sp_col = a.sp_col;
+    return gm;
+}
+
+template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
+__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, KL, BLOCK, AT>()))
+    strip_kernel(const StripArgs a)
+{
+    __shared__ AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
+    const Geom gm = geom_of(a);
     strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, blockIdx.x, blockIdx.y, lds, nullptr, nullptr);
+}
+
+// FP32 forward with the separable spatial kernel (NSC non-zero frequencies,
+// SEVEN: the zero frequency present), one order per pipeline interval.
+template <int BLOCK, int NSC, bool SEVEN>
+constexpr int spatial_minb()
+{
+    return lds_occupancy(strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>() * 4) >= 2 ? 2 : 1;
+}
+template <int BLOCK, int KR, int NSC, bool SEVEN>
+__global__ void __launch_bounds__(BLOCK, (spatial_minb<BLOCK, NSC, SEVEN>())) spatial_kernel(const StripArgs a)
+{
+    __shared__ float lds[strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>()];
+    const Geom gm = geom_of(a);
+    strip_body<float, BLOCK, KR, 1, PolForward<float>, 0, false, NSC, SEVEN>(a.io, gm, blockIdx.x, blockIdx.y,
+                                                                             lds, nullptr, nullptr);
+}
+
+// Phase table of the spatial kernel: (cos, sin)(nu_j y) for y < n, the angle
+// reduced modulo 2 pi in FP64 before rounding to FP32.
+__global__ void __launch_bounds__(256) phase_table_kernel(int n, int nsc, double nu0, double nu1, double nu2,
+                                                           float *tab)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n * nsc) return;
+    const int j = idx / n, y = idx - j * n;
+    const double nu = j == 0 ? nu0 : j == 1 ? nu1 : nu2;
+    double ang = nu * (double)y;
+    ang -= 6.283185307179586 * rint(ang * 0.15915494309189535);
+    tab[2 * idx] = (float)cos(ang);
+    tab[2 * idx + 1] = (float)sin(ang);
 }
 
 template <int BLOCK, int KR, int KL, int MINB = 0>
@@ -64,21 +105,7 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward
 {
     __shared__ float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
     __shared__ double red_lds[BLOCK];
-    Geom gm;
-    gm.H = a.io.H;
-    gm.W = a.io.W;
-    gm.pitch_in = a.io.pitch_in;
-    gm.pitch_out = a.io.pitch_out;
-    gm.rh = a.rh;
-    gm.rv = a.rv;
-    gm.S = a.S;
-    gm.K = a.K;
-    gm.start_mode = a.start_mode;
-    gm.omega_base = a.omega_base;
-    gm.delta = a.delta;
-    gm.v = a.v;
-    gm.vf = a.vf;
-    gm.ws = a.ws;
+    const Geom gm = geom_of(a);
     strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(
         a.io, gm, blockIdx.x, blockIdx.y, lds, red_lds, a.red + (blockIdx.y * gridDim.x + blockIdx.x));
 }
@@ -205,6 +232,66 @@ static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
     if (kc == KR) return bwd<BLOCK, KR, KL, 0>(a, s, occ);
     // the half pass of 256 lanes fits three workgroups per compute unit
     return bwd<BLOCK, KR / 2, (KL < KR / 2 ? KL : KR / 2), BLOCK == 256 ? 3 : 0>(a, s, occ);
+}
+
+// Spatial kernel: orders per pass by the number of frequencies (the complex
+// running sums take 2 NSC registers per channel and order next to the plain one).
+constexpr int kr_spatial(int nsc) { return nsc == 1 ? 4 : 2; }
+int chunk_spatial_f32(int block, int nsc)
+{
+    (void)block;
+    return kr_spatial(nsc);
+}
+// 512-lane strips hold the LDS rows of at most two frequencies
+bool spatial_block_ok(int block, int nsc) { return block == 256 || (block == 512 && nsc <= 2); }
+
+template <int BLOCK, int NSC, bool SEVEN>
+static hipError_t spatial_go(const StripArgs &a, hipStream_t s, int *occ)
+{
+    constexpr int KR = kr_spatial(NSC);
+    if (occ) return query_occupancy((const void *)spatial_kernel<BLOCK, KR, NSC, SEVEN>, BLOCK, occ);
+    const int Wt = BLOCK - 2 * a.rh;
+    if (Wt < 1) return hipErrorInvalidValue;
+    dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
+    hipLaunchKernelGGL((spatial_kernel<BLOCK, KR, NSC, SEVEN>), grid, dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int BLOCK, int MAXNSC>
+static hipError_t spatial_block(const StripArgs &a, const SpatialPlan &sp, hipStream_t s, int *occ)
+{
+    switch (sp.nsc * 2 + (sp.even ? 1 : 0)) {
+    case 2: return spatial_go<BLOCK, 1, false>(a, s, occ);
+    case 3: return spatial_go<BLOCK, 1, true>(a, s, occ);
+    case 4: return spatial_go<BLOCK, 2, false>(a, s, occ);
+    case 5: return spatial_go<BLOCK, 2, true>(a, s, occ);
+    case 6:
+        if constexpr (MAXNSC >= 3) return spatial_go<BLOCK, 3, false>(a, s, occ);
+        return hipErrorInvalidValue;
+    case 7:
+        if constexpr (MAXNSC >= 3) return spatial_go<BLOCK, 3, true>(a, s, occ);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, hipStream_t s, int *occ)
+{
+    if (!spatial_block_ok(block, sp.nsc)) return hipErrorInvalidValue;
+    switch (block) {
+    case 256: return spatial_block<256, 3>(a, sp, s, occ);
+    case 512: return spatial_block<512, 2>(a, sp, s, occ);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_phase_table(const SpatialPlan &sp, int n, float *tab, hipStream_t s)
+{
+    const long total = (long)n * sp.nsc;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(phase_table_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, sp.nsc,
+                       sp.nu[0], sp.nu[1], sp.nu[2], tab);
+    return hipGetLastError();
 }
 
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,

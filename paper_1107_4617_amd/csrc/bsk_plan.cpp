@@ -102,4 +102,30 @@ int make_plan(int N, double sigma_r, double eps, Plan *p)
     return 0;
 }
 
+int make_spatial_plan(int Ns, double sigma_s, SpatialPlan *sp)
+{
+    if (Ns < 0 || Ns > 2 * kMaxSpatialFreq || !(sigma_s > 0.0) || !std::isfinite(sigma_s)) return -1;
+    *sp = SpatialPlan();
+    sp->Ns = Ns;
+    sp->sigma = sigma_s;
+    if (Ns == 0) return 0;   // the box
+    // 2^-Ns C(Ns, j), exact for Ns <= 6
+    double c = 1.0;
+    double binom[2 * kMaxSpatialFreq + 1];
+    for (int j = 0; j <= Ns; ++j) {
+        binom[j] = c;
+        c = c * (double)(Ns - j) / (double)(j + 1);
+    }
+    const double scale = std::ldexp(1.0, -Ns);
+    const double unit = 1.0 / (sigma_s * std::sqrt((double)Ns));
+    sp->nsc = (Ns + 1) / 2;
+    sp->even = (Ns % 2) == 0;
+    sp->u0 = sp->even ? binom[Ns / 2] * scale : 0.0;
+    for (int j = 0; j < sp->nsc; ++j) {
+        sp->u[j] = 2.0 * binom[j] * scale;
+        sp->nu[j] = (double)(Ns - 2 * j) * unit;
+    }
+    return 0;
+}
+
 }  // namespace bsk

@@ -14,8 +14,9 @@ import torch
 
 from . import _lib
 
-__all__ = ["bilateral", "bilateral_train", "bilateral_backward", "bilateral_batched", "order_for",
-           "plan_info", "autotune", "BilateralFunction", "ShiftableBilateral", "release"]
+__all__ = ["bilateral", "spatial_filter", "spatial_sigma_for", "bilateral_train", "bilateral_backward",
+           "bilateral_batched", "order_for", "plan_info", "autotune", "BilateralFunction", "ShiftableBilateral",
+           "release"]
 
 
 def _stream():
@@ -35,8 +36,14 @@ def _check_image(t: torch.Tensor, name: str, dtype=torch.float32):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, strip_h=0, order_chunk=0):
+def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, strip_h=0, order_chunk=0,
+             spatial_sigma=None, spatial_N=None):
     o = _lib.Options()
+    if spatial_sigma is not None:
+        o.spatial_sigma = float(spatial_sigma)
+        o.spatial_N = -1 if spatial_N is None else int(spatial_N)
+    elif spatial_N:
+        raise ValueError("spatial_N needs spatial_sigma")
     if N is None:
         o.order_mode = 0
         o.N = 0
@@ -70,12 +77,16 @@ def plan_info(N: int, eps: float = 0.0):
 
 def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,
               precision: str = "fp32", weight_eps: float = 0.0, kahan: bool = False, block: int = 0,
-              strip_h: int = 0, order_chunk: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Bilateral filter with a (2r+1)^2 box window and the range kernel cos^N(t / (sigma_r sqrt N)).
+              strip_h: int = 0, order_chunk: int = 0, out: Optional[torch.Tensor] = None,
+              spatial_sigma: Optional[float] = None, spatial_N: Optional[int] = None) -> torch.Tensor:
+    """Bilateral filter on the (2r+1)^2 window with the range kernel cos^N(t / (sigma_r sqrt N)).
 
     precision: "fp32" (default); "bf16", "fp16" or "i16" (precision form: the cos/sin stack
     quantised to bfloat16, float16 or 16-bit fixed point, FP32 sums); "fp64" (img float64).
     N: None selects N_0(sigma_r, T).  weight_eps > 0 drops binomial weights below it.
+    spatial_sigma: None for the box spatial kernel; otherwise the separable spatial kernel
+    w(dy) w(dx), w(d) = cos^Ns(d / (spatial_sigma sqrt Ns)) (Algorithm 2 with M = (Ns+1)^2),
+    Ns = spatial_N, or the smallest order unimodal on the window when None (at most 6).
     block, strip_h, order_chunk: launch shape (0 = tuned or automatic).
     """
     dt = torch.float64 if precision == "fp64" else torch.float32
@@ -87,12 +98,25 @@ def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, 
         if out.shape != img.shape:
             raise ValueError("out has the wrong shape")
     H, W = img.shape
-    opt = _options(N, precision, weight_eps, kahan, block, strip_h, order_chunk)
+    opt = _options(N, precision, weight_eps, kahan, block, strip_h, order_chunk, spatial_sigma, spatial_N)
     with torch.cuda.device(img.device):
         _lib.check(_lib.load().bilateral_shiftable_ex(
             ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),
             ctypes.c_void_p(out.data_ptr()), ctypes.byref(opt), _stream()))
     return out
+
+
+def spatial_filter(img: torch.Tensor, radius: int, spatial_sigma: float, spatial_N: Optional[int] = None,
+                   out: Optional[torch.Tensor] = None, block: int = 0, strip_h: int = 0) -> torch.Tensor:
+    """Algorithm 1: the normalised linear filter sum_y w(y - x) f(y) / sum_y w(y - x) over the
+    (2r+1)^2 window with the separable raised-cosine spatial kernel (the range order N = 0)."""
+    return bilateral(img, radius, 1.0, 1.0, N=0, out=out, block=block, strip_h=strip_h,
+                     spatial_sigma=spatial_sigma, spatial_N=spatial_N)
+
+
+def spatial_sigma_for(T_s: float, Ns: int) -> float:
+    """spatial_sigma giving the paper's q_Ns(t) = cos^Ns(pi t / (2 T_s)) (Section 3)."""
+    return 2.0 * float(T_s) / (math.pi * math.sqrt(int(Ns)))
 
 
 def bilateral_train(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None):

@@ -175,3 +175,41 @@ def test_python_layer_rejects_cpu_tensors():
     from paper_1107_4617_amd import bilateral
     with pytest.raises(TypeError):
         bilateral(torch.zeros(4, 4), 1, 30.0)
+
+
+def test_spatial_kernel_errors(lib):
+    """Separable spatial kernel options: invalid values, orders above 6, and the entry points
+    and shapes that do not run it."""
+    big, big2 = 1 << 40, 1 << 41
+
+    def opt(Ns, sigma, **kw):
+        o = _lib.Options()
+        o.spatial_N = Ns
+        o.spatial_sigma = sigma
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, 0.0)) == _lib.BSK_EINVAL
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, float("nan"))) == _lib.BSK_EINVAL
+    assert _call_ex(lib, img=big, out=big2, opt=opt(-2, 2.0)) == _lib.BSK_EINVAL
+    assert _call_ex(lib, img=big, out=big2, opt=opt(7, 2.0)) == _lib.BSK_ERANGE
+    # automatic order: ceil((2 r / (pi sigma_s))^2) = 163 > 6
+    assert _call_ex(lib, img=big, out=big2, r=10, opt=opt(-1, 0.5)) == _lib.BSK_ERANGE
+    assert b"spatial order" in lib.bsk_last_error()
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, 2.0, precision=_lib.BSK_BF16)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, 2.0, kahan=1)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, 2.0, precision=3)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, 2.0, block=1024)) == _lib.BSK_EUNSUPPORTED
+    # three frequencies need 256-lane strips: radius 200 leaves none
+    assert _call_ex(lib, img=big, out=big2, H=500, W=500, r=200, opt=opt(5, 90.0)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(2, 2.0, order_chunk=8)) == _lib.BSK_EINVAL
+    vp = ctypes.c_void_p
+    o = opt(2, 2.0)
+    assert lib.bilateral_shiftable_train(vp(big), 8, 8, 2, 30.0, 255.0, ctypes.byref(o), vp(big2), vp(1 << 42),
+                                         None) == _lib.BSK_EUNSUPPORTED
+    assert lib.bilateral_shiftable_backward(vp(big), vp(big2), None, None, 8, 8, 2, 30.0, 255.0, ctypes.byref(o),
+                                            vp(1 << 43), None, None) == _lib.BSK_EUNSUPPORTED
+    d = (_lib.ImageDesc * 1)()
+    d[0].img, d[0].out, d[0].H, d[0].W, d[0].radius, d[0].sigma_r, d[0].N = big, big2, 8, 8, 2, 30.0, -1
+    assert lib.bilateral_shiftable_batched(d, 1, 255.0, ctypes.byref(o), None) == _lib.BSK_EUNSUPPORTED
