@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -91,9 +92,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="profiling mode: run the headline forward --steps times (after --warmup) and a "
-                         "device copy of --copy-mib MiB, print nothing but a summary line")
+    ap.add_argument("--kernel-only", nargs="?", const="headline", default=None, choices=["headline", "spatial"],
+                    help="profiling mode: run the headline forward (or the spatial-kernel forward at the "
+                         "same size) --steps times after --warmup, and a device copy of --copy-mib MiB; "
+                         "print nothing but a summary line")
     ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -103,7 +105,7 @@ def main():
 
     import torch
     from paper_1107_4617_amd import (bilateral, bilateral_backward, bilateral_batched, bilateral_train,
-                                     plan_info)
+                                     plan_info, spatial_filter, spatial_sigma_for)
     from paper_1107_4617_amd import workloads as wl
 
     dev = torch.device("cuda:0")
@@ -118,7 +120,12 @@ def main():
     out = torch.empty_like(img)
 
     fwd = lambda: bilateral(img, radius, sigma, T, N=N, out=out)  # noqa: E731
+    # the separable q_2 spatial kernel over the same window (Algorithm 2 with M = 9)
+    sig_s = spatial_sigma_for(radius, 2)
+    fwd_sp = lambda: bilateral(img, radius, sigma, T, N=N, out=out, spatial_sigma=sig_s, spatial_N=2)  # noqa: E731
     if args.kernel_only:
+        if args.kernel_only == "spatial":
+            fwd = fwd_sp
         # a plain device copy of known size: reference for the HBM byte counters
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, device=dev)
@@ -188,6 +195,27 @@ def main():
                                   "folded_orders": kb, "dropped_weight": eps,
                                   "max_abs_vs_fp32": float((outq - out).abs().max())}
         del outq
+        # Algorithm 2 with the separable q_2 spatial kernel (M = 9) and Algorithm 1 at the
+        # headline size and window
+        log("timing spatial kernels")
+        ms_sp, _, _ = time_calls(fwd_sp, args.steps, args.warmup, stream)
+        ms_a1, _, _ = time_calls(lambda: spatial_filter(img, radius, sig_s, 2, out=out), args.steps, args.warmup,
+                                 stream)
+        variants["spatial_q2_M9_rect4096_r20_s30"] = {"Mpixel/s": round(px / ms_sp / 1e3, 2), "ms": round(ms_sp, 4),
+                                                      "spatial_sigma": sig_s, "spatial_N": 2,
+                                                      "vs_box": round(mean_ms / ms_sp, 3)}
+        variants["algorithm1_q2_rect4096_r20"] = {"Mpixel/s": round(px / ms_a1 / 1e3, 2), "ms": round(ms_a1, 4)}
+        # the paper's timed instance: 512x512, T = 5 (11x11 window), M x N = 3^2 x 5, i.e. the
+        # spatial q_2 on [-5, 5] and the range q_4 on [-255, 255] (sigma_r = 255 / pi)
+        small = torch.from_numpy(wl.smooth_image(512, 512, seed=1)).to(dev)
+        outs_ = torch.empty_like(small)
+        ms_p, _, _ = time_calls(lambda: bilateral(small, 5, T / math.pi, T, N=4, out=outs_,
+                                                  spatial_sigma=spatial_sigma_for(5, 2), spatial_N=2),
+                                args.steps, args.warmup, stream)
+        variants["paper_instance_512_T5_M9_N5"] = {"ms": round(ms_p, 4),
+                                                   "Mpixel/s": round(512 * 512 / ms_p / 1e3, 2),
+                                                   "paper_matlab_s": 2.5}
+        del small, outs_
         # training forward + adjoint at the headline workload
         g = torch.randn_like(img)
 

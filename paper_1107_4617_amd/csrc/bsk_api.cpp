@@ -97,16 +97,17 @@ int device_cus()
 // ----------------------------------------------------------- validation --
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-// Orders per pass from the pass sizes a kernel family offers (full, full / 2):
+// Orders per pass from the pass sizes a kernel family offers (full and a
+// smaller one, by default full / 2):
 // the one with the lower estimated cost, counting the padded orders each pass
 // runs and about 2.5 + kc / 10 orders' worth of per-pass work (window
 // initialisation, recurrence starts, workspace traffic).
-static int pick_chunk(int K, int full)
+static int pick_chunk(int K, int full, int small = 0)
 {
-    const int half = full / 2;
-    if (half < 1) return full;
+    if (small == 0) small = full / 2;
+    if (small < 1 || small == full) return full;
     auto cost = [K](int kc) { return ((K + kc - 1) / kc) * (kc + 2.5 + 0.1 * kc); };
-    return cost(half) < cost(full) ? half : full;
+    return cost(small) < cost(full) ? small : full;
 }
 
 // Workgroups per compute unit of the kernel a resolved request will launch.
@@ -128,7 +129,7 @@ static int kernel_occupancy(const Resolved &r, int kind)
     std::memset(&a, 0, sizeof(a));
     int occ = 1;
     if (r.sp.Ns > 0) {
-        (void)bsk::launch_spatial_f32(a, r.block, r.sp, nullptr, &occ);
+        (void)bsk::launch_spatial_f32(a, r.block, r.sp, r.kc, nullptr, &occ);
     } else if (kind == kTrain) {
         (void)bsk::launch_train_f32(a, r.block, nullptr, &occ);
     } else if (kind == kBackward) {
@@ -239,9 +240,16 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     if (o.order_chunk < 0) return fail(BSK_EINVAL, "order_chunk must be >= 0");
     int kc = o.order_chunk ? o.order_chunk : tuned_kc;
     if (spatial) {
-        kc = bsk::chunk_spatial_f32(block, r->sp.nsc);
-        if (o.order_chunk && o.order_chunk != kc)
-            return fail(BSK_EINVAL, "order_chunk %d is not the spatial kernel's pass size %d", o.order_chunk, kc);
+        const int full = bsk::chunk_spatial_f32(block, r->sp.nsc);
+        const int small = bsk::chunk_spatial_small_f32(block, r->sp.nsc);
+        if (o.order_chunk) {
+            if (o.order_chunk != full && o.order_chunk != small)
+                return fail(BSK_EINVAL, "order_chunk %d is not a spatial pass size (%d or %d)", o.order_chunk, full,
+                            small);
+            kc = o.order_chunk;
+        } else {
+            kc = pick_chunk(r->plan.K, full, small);
+        }
     } else if (kind == kTrain) {
         kc = bsk::chunk_train_f32(block);
     } else if (kind == kBackward) {
@@ -358,7 +366,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
         for (int j = 0; j < bsk::kMaxSpatialFreq; ++j) a.sp_u[j] = (float)r.sp.u[j];
         a.sp_row = rowtab;
         a.sp_col = coltab;
-        e = bsk::launch_spatial_f32(a, r.block, r.sp, (hipStream_t)stream);
+        e = bsk::launch_spatial_f32(a, r.block, r.sp, r.kc, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "spatial forward launch");
         return BSK_OK;
     }

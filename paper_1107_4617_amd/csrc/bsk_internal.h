@@ -98,12 +98,13 @@ hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *o
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);
 // FP32 forward with the separable spatial kernel of plan sp (nsc >= 1).
-hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, hipStream_t s,
+hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, int kc, hipStream_t s,
                               int *occ = nullptr);
 // Fills tab[2 (j n + y) + {0, 1}] = (cos, sin)(nu[j] y) for y < n, j < sp.nsc, in FP64
 // with the angle reduced modulo 2 pi before rounding to FP32.
 hipError_t launch_phase_table(const SpatialPlan &sp, int n, float *tab, hipStream_t s);
-int chunk_spatial_f32(int block, int nsc);
+int chunk_spatial_f32(int block, int nsc);         // the full pass
+int chunk_spatial_small_f32(int block, int nsc);   // the small pass (the full one where none)
 bool spatial_block_ok(int block, int nsc);
 
 // Orders per pass of the strip kernel for a kernel family/block; the FP32

@@ -235,20 +235,26 @@ static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
 }
 
 // Spatial kernel: orders per pass by the number of frequencies (the complex
-// running sums take 2 NSC registers per channel and order next to the plain one).
+// running sums take 2 NSC registers per channel and order next to the plain
+// one); a full pass and a small one (for few orders, e.g. Algorithm 1).
 constexpr int kr_spatial(int nsc) { return nsc == 1 ? 4 : 2; }
+constexpr int kr_spatial_small(int nsc) { return nsc == 1 ? 2 : 1; }
 int chunk_spatial_f32(int block, int nsc)
 {
     (void)block;
     return kr_spatial(nsc);
 }
+int chunk_spatial_small_f32(int block, int nsc)
+{
+    // the 512-lane strips offer the full pass only
+    return block == 256 ? kr_spatial_small(nsc) : kr_spatial(nsc);
+}
 // 512-lane strips hold the LDS rows of at most two frequencies
 bool spatial_block_ok(int block, int nsc) { return block == 256 || (block == 512 && nsc <= 2); }
 
-template <int BLOCK, int NSC, bool SEVEN>
-static hipError_t spatial_go(const StripArgs &a, hipStream_t s, int *occ)
+template <int BLOCK, int NSC, bool SEVEN, int KR>
+static hipError_t spatial_launch(const StripArgs &a, hipStream_t s, int *occ)
 {
-    constexpr int KR = kr_spatial(NSC);
     if (occ) return query_occupancy((const void *)spatial_kernel<BLOCK, KR, NSC, SEVEN>, BLOCK, occ);
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
@@ -257,30 +263,41 @@ static hipError_t spatial_go(const StripArgs &a, hipStream_t s, int *occ)
     return hipGetLastError();
 }
 
+template <int BLOCK, int NSC, bool SEVEN>
+static hipError_t spatial_go(const StripArgs &a, int kc, hipStream_t s, int *occ)
+{
+    if (kc == kr_spatial(NSC)) return spatial_launch<BLOCK, NSC, SEVEN, kr_spatial(NSC)>(a, s, occ);
+    if constexpr (BLOCK == 256) {
+        if (kc == kr_spatial_small(NSC)) return spatial_launch<BLOCK, NSC, SEVEN, kr_spatial_small(NSC)>(a, s, occ);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int BLOCK, int MAXNSC>
-static hipError_t spatial_block(const StripArgs &a, const SpatialPlan &sp, hipStream_t s, int *occ)
+static hipError_t spatial_block(const StripArgs &a, const SpatialPlan &sp, int kc, hipStream_t s, int *occ)
 {
     switch (sp.nsc * 2 + (sp.even ? 1 : 0)) {
-    case 2: return spatial_go<BLOCK, 1, false>(a, s, occ);
-    case 3: return spatial_go<BLOCK, 1, true>(a, s, occ);
-    case 4: return spatial_go<BLOCK, 2, false>(a, s, occ);
-    case 5: return spatial_go<BLOCK, 2, true>(a, s, occ);
+    case 2: return spatial_go<BLOCK, 1, false>(a, kc, s, occ);
+    case 3: return spatial_go<BLOCK, 1, true>(a, kc, s, occ);
+    case 4: return spatial_go<BLOCK, 2, false>(a, kc, s, occ);
+    case 5: return spatial_go<BLOCK, 2, true>(a, kc, s, occ);
     case 6:
-        if constexpr (MAXNSC >= 3) return spatial_go<BLOCK, 3, false>(a, s, occ);
+        if constexpr (MAXNSC >= 3) return spatial_go<BLOCK, 3, false>(a, kc, s, occ);
         return hipErrorInvalidValue;
     case 7:
-        if constexpr (MAXNSC >= 3) return spatial_go<BLOCK, 3, true>(a, s, occ);
+        if constexpr (MAXNSC >= 3) return spatial_go<BLOCK, 3, true>(a, kc, s, occ);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, hipStream_t s, int *occ)
+hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, int kc, hipStream_t s,
+                              int *occ)
 {
     if (!spatial_block_ok(block, sp.nsc)) return hipErrorInvalidValue;
     switch (block) {
-    case 256: return spatial_block<256, 3>(a, sp, s, occ);
-    case 512: return spatial_block<512, 2>(a, sp, s, occ);
+    case 256: return spatial_block<256, 3>(a, sp, kc, s, occ);
+    case 512: return spatial_block<512, 2>(a, sp, kc, s, occ);
     default: return hipErrorInvalidValue;
     }
 }
