@@ -102,7 +102,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // the one with the lower estimated cost, counting the padded orders each pass
 // runs and about 2.5 + kc / 10 orders' worth of per-pass work (window
 // initialisation, recurrence starts, workspace traffic).
-static int pick_chunk(int K, int full, int small = 0)
+int pick_chunk(int K, int full, int small)
 {
     if (small == 0) small = full / 2;
     if (small < 1 || small == full) return full;

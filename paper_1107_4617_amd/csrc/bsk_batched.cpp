@@ -86,17 +86,20 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     if (block != 256 && block != 512 && block != 1024) return fail(BSK_EINVAL, "block must be 256, 512 or 1024");
     if (max_rh > bsk::max_radius_batched(block))
         return fail(BSK_EUNSUPPORTED, "clamped radius %d too large for a %d-lane strip", max_rh, block);
-    const int kc = bsk::chunk_batched_f32(block);
+    const int kfull = bsk::chunk_batched_f32(block);
     const int rows = o.strip_h > 0 ? o.strip_h : kBatchRows;
     for (auto &it : items) {
         const int Wt = block - 2 * it.im.rh;
         it.im.strips = (it.im.W + Wt - 1) / Wt;
         it.im.S = std::min(rows, it.im.H);
+        // per image: the full pass or its half, whichever pads fewer orders for the cost
+        it.im.kc = pick_chunk(it.im.K, kfull);
+        const int kc = it.im.kc;
         const int segs = (it.im.H + it.im.S - 1) / it.im.S;
-        // work of one unit ~ lanes x (rows + window) x (orders + per-pass cost)
+        // work of one unit ~ lanes x (rows + window) x (padded orders + per-pass cost)
         const int passes = (it.im.K + kc - 1) / kc;
         it.cost = (double)it.im.strips * segs * block * (it.im.S + 0.25 * 2 * it.im.rv) *
-                  (it.im.K + 2.0 * passes);
+                  (passes * kc + 2.0 * passes);
     }
     // most expensive images first, so the tail of the persistent loop is short units
     std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
@@ -115,6 +118,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         if (units > (1LL << 30)) return fail(BSK_EINVAL, "too many work units");
         it.im.v_off = (int)bp->vtab.size();
         // pad to whole passes with zero weights
+        const int kc = it.im.kc;
         it.im.K = (it.im.K + kc - 1) / kc * kc;
         it.v.resize(it.im.K, 0.0);
         bp->vtab.insert(bp->vtab.end(), it.v.begin(), it.v.end());

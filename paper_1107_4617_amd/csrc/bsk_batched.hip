@@ -71,8 +71,13 @@ __global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const
         gm.sp_u0 = 1.0f;   // the box spatial kernel
         for (int j = 0; j < kMaxSpatialFreq; ++j) gm.sp_u[j] = 0.0f;
         gm.sp_row = gm.sp_col = nullptr;
-        strip_body<float, BLOCK, KC, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
-                                                                                    nullptr, nullptr);
+        // the image's pass size: the full pass or its half (same LDS shape)
+        if (im.kc == KC)
+            strip_body<float, BLOCK, KC, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
+                                                                                        nullptr, nullptr);
+        else
+            strip_body<float, BLOCK, KC / 2, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
+                                                                                            nullptr, nullptr);
         __syncthreads();
     }
 }

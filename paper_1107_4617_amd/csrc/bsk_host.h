@@ -33,6 +33,9 @@ struct Resolved {
 enum Kind { kForward = 0, kTrain = 1, kBackward = 2 };
 int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r,
             int kind = kForward);
+// Orders per pass from a kernel family's full pass and a smaller one (0: half
+// the full one): the one with the lower estimated cost for K orders.
+int pick_chunk(int K, int full, int small = 0);
 // Fills the launch arguments; the weights are padded with zeros to a multiple
 // of `kc` (the pass size of the kernel that will run).
 void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W, int kc);

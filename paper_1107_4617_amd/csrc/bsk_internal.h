@@ -126,6 +126,7 @@ struct BatchImage {
     int H, W, rh, rv, S, K;
     int start_mode;          // as in StripArgs
     int strips;
+    int kc;                  // orders per pass: the batched kernel's full pass or its half
     int unit0;               // first work unit of this image
     long long ws_off;        // offset of this image's accumulator planes in ws, -1 if none
     int v_off;               // offset of this image's weights in the weight table

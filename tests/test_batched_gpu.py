@@ -29,9 +29,9 @@ def test_batched_equals_single_image_path_and_oracle():
     outs = bilateral_batched(imgs, [s[2] for s in specs], [s[3] for s in specs], T)
     torch.cuda.synchronize()
     for (H, W, r, sg, _), x, y in zip(specs, imgs, outs):
-        # same launch shape (256 lanes, 16 orders per pass, 64-row units) gives the
-        # same arithmetic
-        single = bilateral(x, r, sg, T, block=256, strip_h=64, order_chunk=16)
+        # same launch shape (256 lanes, 64-row units, the pass size both paths choose
+        # for the image's order count) gives the same arithmetic
+        single = bilateral(x, r, sg, T, block=256, strip_h=64)
         torch.cuda.synchronize()
         assert torch.equal(single, y)
     for b in (0, 5, 13):
@@ -69,7 +69,7 @@ def test_full_batch_256_images():
     rng = np.random.default_rng(4)
     for b in rng.choice(256, 6, replace=False):
         H, W, r, sg, _ = specs[b]
-        single = bilateral(imgs[b], r, sg, T, block=256, strip_h=64, order_chunk=16)
+        single = bilateral(imgs[b], r, sg, T, block=256, strip_h=64)
         torch.cuda.synchronize()
         assert torch.equal(single, outs[b])
         f = imgs[b].cpu().numpy()
