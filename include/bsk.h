@@ -5,8 +5,11 @@
  * Method (K. N. Chaudhury, "Constant-time filtering using shiftable kernels"):
  * eq. (3) of Section 2 defines the bilateral filter
  *     out(x) = sum_{y in B(x)} phi(f(y) - f(x)) f(y)  /  sum_{y in B(x)} phi(f(y) - f(x)).
- * Here the spatial kernel is a box: B(x) is the (2r+1)x(2r+1) square centred
- * at x, truncated at the image border (pixels outside the image are absent).
+ * B(x) is the (2r+1)x(2r+1) square centred at x, truncated at the image
+ * border (pixels outside the image are absent).  The spatial kernel is a box
+ * by default (every pixel of B(x) has weight 1); bsk_options selects instead
+ * the separable raised cosine of Section 3 (Algorithm 2 with M > 1 spatial
+ * basis functions, and Algorithm 1 when the range order is 0).
  * The range kernel is the raised cosine q_N of Section 3 in the scaling of
  * Theorem 3.3, eq. (6): phi(t) = cos^N(t / (sigma_r sqrt N)), which tends to
  * the Gaussian exp(-t^2 / 2 sigma_r^2).  Being a finite sum of N+1 complex
@@ -69,7 +72,8 @@ typedef enum {
 #define BSK_MAX_RADIUS 500     /* clamped radius limit of the fused kernels */
 
 /* Options; a zero-initialised struct means: automatic N_0, FP32, no
- * truncation, no compensation, dense pitch, tuned launch shape. */
+ * truncation, no compensation, dense pitch, tuned launch shape, box spatial
+ * kernel. */
 typedef struct {
     int order_mode;       /* 0: N = N_0 from sigma_r and T; 1: use `N` below */
     int N;                /* range-kernel order when order_mode == 1 (N = 0 is the box mean) */
@@ -80,8 +84,11 @@ typedef struct {
     int pitch_out;        /* output row pitch in elements; 0 = W */
     int block;            /* lanes per workgroup (256, 512, 1024); 0 = auto */
     int strip_h;          /* output rows per workgroup; 0 = auto */
-    int order_chunk;      /* FP32 forward: orders per pass, the full or the half pass of the
-                             block (256: 16|8, 512: 8|4, 1024: 4|2); 0 = auto */
+    int order_chunk;      /* orders per pass, one of the two pass sizes of the kernel that runs:
+                             FP32 forward 256: 16|8, 512: 8|4, 1024: 4|2 (lanes: full|half);
+                             adjoint 256: 16|8, 512: 8|4, 1024: 2|1; spatial kernel 4|2
+                             (one frequency) or 2|1; ignored by FP64 and the training
+                             forward; 0 = automatic (the cheaper for the order count) */
     /* Spatial kernel (Algorithms 1 and 2 with M > 1; Section 3, separable
      * kernels): 0 = the box; Ns in 1..6 = the separable raised cosine
      * w(dy) w(dx), w(d) = cos^Ns(d / (spatial_sigma sqrt Ns)) on the same

@@ -4,6 +4,7 @@ functions, and Algorithm 1 as its N = 0 case) against the FP64 oracle, through t
 Tolerance: the FP32 bound of the box path, 1e-4 T (T = 255), max-abs over every compared
 pixel.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -11,7 +12,8 @@ import pytest
 import torch
 
 import oracle
-from paper_1107_4617_amd import bilateral, spatial_filter, spatial_sigma_for
+from paper_1107_4617_amd import _lib, bilateral, spatial_filter, spatial_sigma_for
+from paper_1107_4617_amd import filter as F
 from paper_1107_4617_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -109,3 +111,20 @@ def test_spatial_large_image_sampled():
                                     rng.integers(0, 2048, 200) * 2048 + 2047]))
     ref = oracle.bilateral_sp_at(f, idx, 5, 30.0, 30, sigma_s, 2)
     assert np.max(np.abs(out.ravel()[idx] - ref)) <= TOL32
+
+
+def test_spatial_pitch():
+    """Row pitches larger than the width: the spatial path reads and writes through them."""
+    f = wl.rect_image(45, 70, seed=13)
+    base = torch.zeros((45, 96), dtype=torch.float32, device="cuda")
+    base[:, :70] = torch.from_numpy(f).cuda()
+    outp = torch.full((45, 128), -7.0, dtype=torch.float32, device="cuda")
+    o = F._options(30, spatial_sigma=2.5, spatial_N=2)
+    o.pitch_in, o.pitch_out = 96, 128
+    _lib.check(_lib.load().bilateral_shiftable_ex(ctypes.c_void_p(base.data_ptr()), 45, 70, 4, 30.0, T,
+                                                  ctypes.c_void_p(outp.data_ptr()), ctypes.byref(o), F._stream()))
+    torch.cuda.synchronize()
+    got = outp.cpu().numpy()
+    ref = oracle.bilateral_sp(f, 4, 30.0, 30, 2.5, 2)
+    assert np.max(np.abs(got[:, :70] - ref)) <= TOL32
+    assert np.all(got[:, 70:] == -7.0)
