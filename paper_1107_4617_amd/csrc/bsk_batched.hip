@@ -25,7 +25,7 @@ __global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
 template <int BLOCK, int KC>
 __global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const BatchArgs a)
 {
-    __shared__ float lds[strip_lds_elems<PolForward<float>::NCH, kl_batched(BLOCK), BLOCK>()];
+    __shared__ __align__(16) float lds[strip_lds_elems<PolForward<float>::NCH, kl_batched(BLOCK), BLOCK>()];
     __shared__ int unit_sh;
     for (;;) {
         if (threadIdx.x == 0) unit_sh = (int)atomicAdd(a.counter, 1u);

@@ -375,9 +375,28 @@ template <>
 __device__ __forceinline__ double weight<double>(const Geom &gm, int m) { return gm.v[m]; }
 
 
+// Two values of the compute type, moved between registers and LDS as one
+// 64-bit (FP32) or 128-bit (FP64) access.
+template <typename AT>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+    __device__ static float2 make(float a, float b) { return make_float2(a, b); }
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+    __device__ static double2 make(double a, double b) { return make_double2(a, b); }
+};
+
 // Walker geometry of one LDS row of BLOCK columns.  The row holds column c at
 // position c (a contiguous run of lanes touches distinct banks) and, after the
 // H stage, the exclusive prefix sum E(c) = sum_{j < c} V(j), for c = 0 .. BLOCK.
+// The two rows of a channel pair (the cosine and the sine member) are stored
+// interleaved, element by element, so the V stage writes and the R stage reads
+// both members with one wide access; a walker steps through its row with
+// stride 2.
 // CH walkers (a power of two, at most one wavefront) per row each own G
 // consecutive positions, G odd: walker w starts at position G w, so the CH
 // walkers of a row start on distinct banks, and rows in the same half
@@ -515,7 +534,10 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     const int wch = t - wrow * CH;
     constexpr bool ALLWALK = ROWS * CH == BLOCK;
     const bool walker = ALLWALK || wrow < ROWS;
-    const int wbase = wrow * RS + wch * G;
+    // row r of a buffer is member (r & 1) of pair-row r >> 1: element u of this
+    // walker's chunk sits at wbase + 2 u
+    const int wbase = (wrow >> 1) * (2 * RS) + 2 * (wch * G) + (wrow & 1);
+    using V2 = typename Vec2<AT>::type;
     // box sum of output lane t: E(t + rh + 1) - E(t - rh)
     const int phi = t + rh + 1;
     const int plo = t - rh;
@@ -656,9 +678,9 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 if (!(actV || actH || actR)) continue;
                 const int bH = bv == 0 ? kNBuf - 1 : bv - 1;
                 const int bR = bH == 0 ? kNBuf - 1 : bH - 1;
-                AT *const VbV = lds + bv * BUF;
+                V2 *const VbV = reinterpret_cast<V2 *>(lds + bv * BUF);
                 AT *const VbH = lds + bH * BUF;
-                const AT *const VbR = lds + bR * BUF;
+                const V2 *const VbR = reinterpret_cast<const V2 *>(lds + bR * BUF);
 
                 // ---- R stage: box sums of the orders sR KL .. of row iR, recombined
                 if (actR && outlane) {
@@ -674,25 +696,32 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         const int m = sR * KL + k;
                         AT B[NCH];
 #pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            const AT *row = VbR + (k * NCH + c) * NB * RS;
+                        for (int p = 0; p < NPAIR; ++p) {
+                            // pair-row of channels (2p, 2p + 1), horizontal basis function b
+                            const V2 *prow = VbR + (k * NPAIR + p) * NB * RS;
                             if constexpr (NSC == 0) {
-                                B[c] = row[phi] - row[plo];
+                                const V2 hi = prow[phi], lo = prow[plo];
+                                B[2 * p] = hi.x - lo.x;
+                                B[2 * p + 1] = hi.y - lo.y;
                             } else {
-                                AT hq = AT(0);
+                                AT h0 = AT(0), h1 = AT(0);
                                 int b = 0;
                                 if constexpr (SEVEN) {
-                                    hq = u0 * (row[phi] - row[plo]);
+                                    const V2 hi = prow[phi], lo = prow[plo];
+                                    h0 = u0 * (hi.x - lo.x);
+                                    h1 = u0 * (hi.y - lo.y);
                                     b = 1;
                                 }
 #pragma unroll
                                 for (int j = 0; j < NSC; ++j) {
-                                    const AT *rc_ = row + (b + 2 * j) * RS;
-                                    const AT *rs_ = rc_ + RS;
-                                    hq = fmat(rcw[j], rc_[phi] - rc_[plo], hq);
-                                    hq = fmat(rsw[j], rs_[phi] - rs_[plo], hq);
+                                    const V2 *rc_ = prow + (b + 2 * j) * RS;
+                                    const V2 *rs_ = rc_ + RS;
+                                    const V2 ch = rc_[phi], cl = rc_[plo], sh = rs_[phi], sl = rs_[plo];
+                                    h0 = fmat(rsw[j], sh.x - sl.x, fmat(rcw[j], ch.x - cl.x, h0));
+                                    h1 = fmat(rsw[j], sh.y - sl.y, fmat(rcw[j], ch.y - cl.y, h1));
                                 }
-                                B[c] = hq;
+                                B[2 * p] = h0;
+                                B[2 * p + 1] = h1;
                             }
                         }
                         const AT v = weight<AT>(gm, m0 + m);
@@ -708,7 +737,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     AT run = AT(0);
                     if (walker) {
 #pragma unroll
-                        for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + u];
+                        for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
 #pragma unroll
                         for (int u = 0; u < G; ++u) {
                             const AT x = loc[u];
@@ -719,7 +748,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     const AT off = group_exclusive_scan<CH>(run, wch);
                     if (walker) {
 #pragma unroll
-                        for (int u = 0; u < G; ++u) VbH[wbase + u] = loc[u] + off;
+                        for (int u = 0; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
                     }
                 }
 
@@ -793,24 +822,30 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                             }
                         }
 #pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            AT *row = VbV + (k * NCH + c) * NB * RS + vpos;
+                        for (int p = 0; p < NPAIR; ++p) {
+                            V2 *prow = VbV + (k * NPAIR + p) * NB * RS + vpos;
                             if constexpr (NSC == 0) {
-                                row[0] = V[m][c];
+                                prow[0] = Vec2<AT>::make(V[m][2 * p], V[m][2 * p + 1]);
                             } else {
-                                // vertically weighted sum, then its horizontal basis rows
-                                AT vq = PLAIN ? u0 * V[m][c] : AT(0);
+                                // vertically weighted sums of the pair, then their horizontal basis rows
+                                AT vq[2];
 #pragma unroll
-                                for (int j = 0; j < NSC; ++j) vq = fmat(ds[j], Wi[m][c][j], fmat(dc[j], Wr[m][c][j], vq));
+                                for (int e = 0; e < 2; ++e) {
+                                    const int c = 2 * p + e;
+                                    vq[e] = PLAIN ? u0 * V[m][c] : AT(0);
+#pragma unroll
+                                    for (int j = 0; j < NSC; ++j)
+                                        vq[e] = fmat(ds[j], Wi[m][c][j], fmat(dc[j], Wr[m][c][j], vq[e]));
+                                }
                                 int b = 0;
                                 if constexpr (SEVEN) {
-                                    row[0] = vq;
+                                    prow[0] = Vec2<AT>::make(vq[0], vq[1]);
                                     b = 1;
                                 }
 #pragma unroll
                                 for (int j = 0; j < NSC; ++j) {
-                                    row[(b + 2 * j) * RS] = vq * hc[j];
-                                    row[(b + 2 * j + 1) * RS] = vq * hs[j];
+                                    prow[(b + 2 * j) * RS] = Vec2<AT>::make(vq[0] * hc[j], vq[1] * hc[j]);
+                                    prow[(b + 2 * j + 1) * RS] = Vec2<AT>::make(vq[0] * hs[j], vq[1] * hs[j]);
                                 }
                             }
                         }

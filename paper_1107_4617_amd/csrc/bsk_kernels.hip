@@ -63,7 +63,7 @@ template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAH
 __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, KL, BLOCK, AT>()))
     strip_kernel(const StripArgs a)
 {
-    __shared__ AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
+    __shared__ __align__(16) AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
     const Geom gm = geom_of(a);
     strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, blockIdx.x, blockIdx.y, lds, nullptr, nullptr);
 }
@@ -78,7 +78,7 @@ constexpr int spatial_minb()
 template <int BLOCK, int KR, int NSC, bool SEVEN>
 __global__ void __launch_bounds__(BLOCK, (spatial_minb<BLOCK, NSC, SEVEN>())) spatial_kernel(const StripArgs a)
 {
-    __shared__ float lds[strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>()];
+    __shared__ __align__(16) float lds[strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>()];
     const Geom gm = geom_of(a);
     strip_body<float, BLOCK, KR, 1, PolForward<float>, 0, false, NSC, SEVEN>(a.io, gm, blockIdx.x, blockIdx.y,
                                                                              lds, nullptr, nullptr);
@@ -103,7 +103,7 @@ template <int BLOCK, int KR, int KL, int MINB = 0>
 __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
     backward_kernel(const StripArgs a)
 {
-    __shared__ float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
+    __shared__ __align__(16) float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
     __shared__ double red_lds[BLOCK];
     const Geom gm = geom_of(a);
     strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(
