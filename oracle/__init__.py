@@ -7,7 +7,9 @@ nor links anything here, and nothing here imports the product package.
 The C source (``bsk_oracle.c``) evaluates eq. (3) of the paper directly with a
 box spatial window and the rescaled raised-cosine range kernel of eq. (6),
 cos^N(t / (sigma_r sqrt N)); the ``*_sp`` entry points add the separable
-raised-cosine spatial kernel of Algorithms 1 and 2 with M > 1.  See its header
+raised-cosine spatial kernel of Algorithms 1 and 2 with M > 1, and the
+``*_poly`` entry points use the polynomial range kernel p_N of Section 3 in the
+scaling of eq. (5), (1 - t^2 / (2 N sigma_r^2))^N.  See its header
 for the definitions.  This module only marshals NumPy arrays.
 """
 from __future__ import annotations
@@ -80,6 +82,19 @@ def _load():
     lib.oracle_bilateral_sp_at.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int, ctypes.c_double, ctypes.c_int, _llp, ctypes.c_longlong,
                                            _dp, _dp, _dp]
+    lib.oracle_poly_order_for.restype = ctypes.c_int
+    lib.oracle_poly_order_for.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.oracle_poly_kernel.restype = ctypes.c_double
+    lib.oracle_poly_kernel.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_bilateral_poly_f64.restype = None
+    lib.oracle_bilateral_poly_f64.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_bilateral_poly.restype = None
+    lib.oracle_bilateral_poly.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_bilateral_poly_at.restype = None
+    lib.oracle_bilateral_poly_at.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_int, _llp, ctypes.c_longlong, _dp]
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -195,4 +210,42 @@ def bilateral_sp_at(f, idx, radius: int, sigma_r: float, N: int, sigma_s: float,
     out = np.empty(idx.size, np.float64)
     _load().oracle_bilateral_sp_at(_ptr(f, _fp), H, W, int(radius), float(sigma_r), int(N), float(sigma_s),
                                    int(Ns), _ptr(idx, _llp), idx.size, _ptr(out, _dp), None, None)
+    return out
+
+
+def poly_order_for(sigma_r: float, T: float) -> int:
+    """Smallest N keeping the polynomial kernel non-negative and unimodal on [-T, T]."""
+    return _load().oracle_poly_order_for(float(sigma_r), float(T))
+
+
+def poly_kernel(t: float, sigma_r: float, N: int) -> float:
+    """(1 - t^2 / (2 N sigma_r^2))^N; 1 for N = 0."""
+    return _load().oracle_poly_kernel(float(t), float(sigma_r), int(N))
+
+
+def bilateral_poly(f, radius: int, sigma_r: float, N: int, return_pq: bool = False):
+    """Whole image with the polynomial range kernel and the box window."""
+    f = np.ascontiguousarray(f)
+    H, W = f.shape
+    out = np.empty((H, W), np.float64)
+    P = np.empty((H, W), np.float64) if return_pq else None
+    Q = np.empty((H, W), np.float64) if return_pq else None
+    if f.dtype == np.float64:
+        _load().oracle_bilateral_poly_f64(_ptr(f, _dp), H, W, int(radius), float(sigma_r), int(N),
+                                          _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    else:
+        f32 = np.ascontiguousarray(f, dtype=np.float32)
+        _load().oracle_bilateral_poly(_ptr(f32, _fp), H, W, int(radius), float(sigma_r), int(N),
+                                      _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    return (out, P, Q) if return_pq else out
+
+
+def bilateral_poly_at(f, idx, radius: int, sigma_r: float, N: int):
+    """The polynomial-kernel filter at the flat (row-major) pixel indices ``idx`` only."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    H, W = f.shape
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size, np.float64)
+    _load().oracle_bilateral_poly_at(_ptr(f, _fp), H, W, int(radius), float(sigma_r), int(N),
+                                     _ptr(idx, _llp), idx.size, _ptr(out, _dp))
     return out

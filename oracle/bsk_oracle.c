@@ -39,6 +39,14 @@
  * The *_sp functions add the separable raised-cosine spatial kernel of
  * Algorithms 1 and 2 with M > 1 (defined with oracle_spatial_weight below).
  *
+ * The *_poly functions use instead the polynomial range kernel p_N of
+ * Section 3 in the scaling of the Gaussian-approximation theorem, eq. (5):
+ * p_N(t / sqrt N) with the bound T of p_N set to sqrt(2) sigma_r, i.e.
+ * phi(t) = (1 - t^2 / (2 N sigma_r^2))^N, which tends to
+ * exp(-t^2 / (2 sigma_r^2)).  A polynomial is shiftable (Section 1), so the
+ * method again reaches the definition exactly and the oracle is the
+ * definition, evaluated directly (no expansion).
+ *
  * Conventions: images are row-major, H rows by W columns; float inputs are
  * widened exactly to double; accumulation is sequential in row-major window
  * order; rows are distributed over OpenMP threads.
@@ -129,10 +137,30 @@ double oracle_trunc_kernel(double t, double sigma_r, int N, double eps)
     return acc;
 }
 
-/* Kernel selector: exact raised cosine, or its truncated expansion.  The
- * truncated kernel is tabulated once per call (weights and frequencies). */
+/* Smallest order N for which the polynomial kernel below is non-negative
+ * and unimodal on [-T, T]: its zeros +-sigma_r sqrt(2N) must lie outside,
+ * N >= T^2 / (2 sigma_r^2). */
+int oracle_poly_order_for(double sigma_r, double T)
+{
+    double x = T / sigma_r;
+    return (int)ceil(0.5 * x * x);
+}
+
+/* Polynomial range kernel phi(t) = (1 - t^2 / (2 N sigma_r^2))^N; Section 3,
+ * p_N, in the scaling of eq. (5).  N = 0 gives phi = 1.  Outside the support
+ * |t| <= sigma_r sqrt(2N) the polynomial is evaluated as it stands. */
+double oracle_poly_kernel(double t, double sigma_r, int N)
+{
+    if (N == 0) return 1.0;
+    double u = t / sigma_r;
+    return ipow(1.0 - u * u / (2.0 * (double)N), N);
+}
+
+/* Kernel selector: exact raised cosine, its truncated expansion, or the
+ * polynomial kernel.  The truncated kernel is tabulated once per call
+ * (weights and frequencies). */
 typedef struct {
-    int mode;          /* 0: cos^N, 1: truncated sum */
+    int mode;          /* 0: cos^N, 1: truncated sum, 2: polynomial */
     int N;
     double sigma_r;
     int nterm;
@@ -170,6 +198,7 @@ static void kern_free(kern_t *k)
 static inline double kern_eval(const kern_t *k, double t)
 {
     if (k->mode == 0) return oracle_kernel(t, k->sigma_r, k->N);
+    if (k->mode == 2) return oracle_poly_kernel(t, k->sigma_r, k->N);
     double acc = 0.0;
     for (int n = 0; n < k->nterm; ++n) acc += k->w[n] * cos(k->om[n] * t);
     return acc;
@@ -480,6 +509,72 @@ void oracle_bilateral_sp_at(const float *f, int H, int W, int radius, double sig
     }
     free(ws);
     kern_free(&k);
+}
+
+/* ---- polynomial range kernel (box spatial kernel) ---- */
+
+static void kern_init_poly(kern_t *k, double sigma_r, int N)
+{
+    memset(k, 0, sizeof(*k));
+    k->N = N;
+    k->sigma_r = sigma_r;
+    k->mode = 2;
+}
+
+/* Full image with the polynomial range kernel, double input; out, P, Q may be
+ * NULL independently. */
+void oracle_bilateral_poly_f64(const double *f, int H, int W, int radius, double sigma_r, int N,
+                               double *out, double *P, double *Q)
+{
+    kern_t k;
+    kern_init_poly(&k, sigma_r, N);
+    long r = clamp_radius(radius, H, W);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < H; ++i) {
+        for (long j = 0; j < W; ++j) {
+            double p, q;
+            window_pq(f, H, W, r, &k, i, j, &p, &q);
+            if (out) out[i * W + j] = p / q;
+            if (P) P[i * W + j] = p;
+            if (Q) Q[i * W + j] = q;
+        }
+    }
+}
+
+/* The same with float input (widened exactly). */
+void oracle_bilateral_poly(const float *f, int H, int W, int radius, double sigma_r, int N,
+                           double *out, double *P, double *Q)
+{
+    double *d = widen(f, (long)H * W);
+    oracle_bilateral_poly_f64(d, H, W, radius, sigma_r, N, out, P, Q);
+    free(d);
+}
+
+/* Selected pixels only (flat row-major indices), float input. */
+void oracle_bilateral_poly_at(const float *f, int H, int W, int radius, double sigma_r, int N,
+                              const long long *idx, long long n, double *out)
+{
+    kern_t k;
+    kern_init_poly(&k, sigma_r, N);
+    long r = clamp_radius(radius, H, W);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long long s = 0; s < n; ++s) {
+        long i = (long)(idx[s] / W), j = (long)(idx[s] % W);
+        double fx = (double)f[i * (long)W + j];
+        double p = 0.0, q = 0.0;
+        long y0 = lmax(0, i - r), y1 = lmin(H - 1, i + r);
+        long x0 = lmax(0, j - r), x1 = lmin(W - 1, j + r);
+        for (long y = y0; y <= y1; ++y) {
+            const float *row = f + y * (long)W;
+            for (long x = x0; x <= x1; ++x) {
+                double fy = (double)row[x];
+                double kv = kern_eval(&k, fy - fx);
+                p += kv * fy;
+                q += kv;
+            }
+        }
+        out[s] = p / q;
+    }
 }
 
 int oracle_num_threads(void)

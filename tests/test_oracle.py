@@ -450,3 +450,203 @@ def test_spatial_sampled_matches_full(oracle):
     full = oracle.bilateral_sp(f, 5, 30.0, 30, 2.25, 2)
     idx = np.array([0, 7, 39, 40, 1199, 345, 777])
     assert np.array_equal(oracle.bilateral_sp_at(f, idx, 5, 30.0, 30, 2.25, 2), full.ravel()[idx])
+
+
+# ------------------------------------------------ polynomial range kernel ----
+# Section 3's p_N(t) = (1 - t^2/T^2)^N in the scaling of eq. (5), with T = sqrt(2) sigma_r:
+# phi(t) = (1 - t^2 / (2 N sigma_r^2))^N.
+from fractions import Fraction
+
+
+def _poly_exact(t, sigma, N):
+    """phi(t) as an exact rational through the binomial theorem,
+    (1 - u)^N = sum_m C(N, m) (-u)^m with u = t^2 / (2 N sigma^2); t and sigma rational."""
+    if N == 0:
+        return Fraction(1)
+    u = Fraction(t) ** 2 / (2 * N * Fraction(sigma) ** 2)
+    return sum(math.comb(N, m) * (-u) ** m for m in range(N + 1))
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 5, 37, 145])
+def test_poly_kernel_matches_exact_binomial_expansion(oracle, N):
+    for t in [0, 1, 7, 30, 99, 180, 255]:
+        exact = _poly_exact(t, 30, N)
+        got = oracle.poly_kernel(float(t), 30.0, N)
+        assert abs(got - float(exact)) <= 1e-14 * max(1.0, abs(float(exact))), (t, N)
+
+
+def test_poly_gaussian_limit_rate(oracle):
+    """Eq. (5): p_N(t / sqrt N) tends to the Gaussian; the error decays like 1/N
+    (log(1 - u/N) N = -u - u^2/(2N) - ...)."""
+    sigma = 30.0
+    ts = np.linspace(0.0, 120.0, 241)
+
+    def err(N):
+        return max(abs(oracle.poly_kernel(t, sigma, N) - math.exp(-t * t / (2 * sigma * sigma))) for t in ts)
+
+    e1, e2, e4 = err(50), err(100), err(200)
+    assert e4 < 1e-2
+    assert 1.8 < e1 / e2 < 2.2 and 1.8 < e2 / e4 < 2.2
+
+
+@pytest.mark.parametrize("sigma,expect", [(30.0, 37), (60.0, 10), (15.0, 145), (25.0, 53), (255.0, 1)])
+def test_poly_order_threshold(oracle, sigma, expect):
+    """N_p is the smallest order with the kernel non-negative and non-increasing on [0, T];
+    one order less puts the polynomial's zero sigma sqrt(2N) inside [0, T), past which
+    (1 - u)^N changes sign (odd N) or grows again (even N)."""
+    assert oracle.poly_order_for(sigma, T) == expect
+    ts = np.linspace(0.0, T, 4001)
+    v = np.array([oracle.poly_kernel(t, sigma, expect) for t in ts])
+    assert np.all(v >= 0.0) and np.all(np.diff(v) <= 0.0)
+    base = lambda N: 1 - Fraction(T) ** 2 / (2 * N * Fraction(sigma) ** 2)   # 1 - u at t = T
+    assert base(expect) >= 0
+    if expect > 1:
+        assert base(expect - 1) < 0
+
+
+@pytest.mark.parametrize("r", [1, 4, 11])
+def test_poly_order_zero_is_box_mean(oracle, r):
+    f = wl.random_image(15, 19, 3)
+    assert np.max(np.abs(oracle.bilateral_poly(f, r, 30.0, 0) - _box_mean(f, r))) < 1e-9
+
+
+def _brute_poly_exact(f, r, sigma, N):
+    """Eq. (3) in exact rational arithmetic for an integer-valued image."""
+    H, W = f.shape
+    P = np.empty((H, W))
+    Q = np.empty((H, W))
+    cache = {}
+    for i in range(H):
+        for j in range(W):
+            fx = int(f[i, j])
+            p = q = Fraction(0)
+            for y in range(max(0, i - r), min(H - 1, i + r) + 1):
+                for x in range(max(0, j - r), min(W - 1, j + r) + 1):
+                    fy = int(f[y, x])
+                    d = fy - fx
+                    if d not in cache:
+                        cache[d] = _poly_exact(d, sigma, N)
+                    k = cache[d]
+                    p += k * fy
+                    q += k
+            P[i, j] = float(p)
+            Q[i, j] = float(q)
+    return P, Q
+
+
+@pytest.mark.parametrize("r,N,sigma,shape", [(1, 1, 30, (6, 7)), (2, 37, 30, (7, 9)), (3, 10, 60, (8, 6)),
+                                             (0, 4, 30, (5, 5)), (2, 145, 15, (6, 6))])
+def test_poly_brute_force_exact_rationals(oracle, r, N, sigma, shape):
+    rng = np.random.default_rng(40 + N)
+    f = rng.integers(0, 256, shape).astype(np.float64)
+    Pr, Qr = _brute_poly_exact(f, r, sigma, N)
+    out, P, Q = oracle.bilateral_poly(f, r, float(sigma), N, return_pq=True)
+    nwin = (2 * r + 1) ** 2
+    assert np.max(np.abs(P - Pr)) <= 1e-13 * nwin * T
+    assert np.max(np.abs(Q - Qr)) <= 1e-13 * nwin
+    assert np.max(np.abs(out - Pr / Qr)) <= 1e-12 * T
+
+
+def _monomial_shiftable(f, r, sigma, N):
+    """Algorithm 2 for the polynomial kernel in the monomial basis (its shiftability,
+    Section 1): phi(s - c) = sum_k a_k(c) s^k, so P = sum_k a_k(f_x) Box[f^(k+1)] and
+    Q = sum_k a_k(f_x) Box[f^k].  Data are centred and scaled first (the filter is shift and
+    scale covariant), and the expansion is only well conditioned for small N."""
+    from numpy.polynomial import polynomial as Pl
+    f = f.astype(np.float64)
+    H, W = f.shape
+    mu, rho = 0.5 * (f.min() + f.max()), 0.5 * (f.max() - f.min())
+    g = (f - mu) / rho
+    a2 = 2.0 * N * (sigma / rho) ** 2
+
+    def box(X):
+        S = np.zeros((H + 1, W + 1))
+        S[1:, 1:] = np.cumsum(np.cumsum(X, 0), 1)
+        i = np.arange(H)[:, None]
+        j = np.arange(W)[None, :]
+        y0, y1 = np.maximum(i - r, 0), np.minimum(i + r, H - 1) + 1
+        x0, x1 = np.maximum(j - r, 0), np.minimum(j + r, W - 1) + 1
+        return S[y1, x1] - S[y0, x1] - S[y1, x0] + S[y0, x0]
+
+    M = [box(g ** k) for k in range(2 * N + 2)]
+    P = np.zeros((H, W))
+    Q = np.zeros((H, W))
+    for i in range(H):
+        for j in range(W):
+            c = g[i, j]
+            a = Pl.polypow([1.0 - c * c / a2, 2.0 * c / a2, -1.0 / a2], N)
+            Q[i, j] = sum(a[k] * M[k][i, j] for k in range(len(a)))
+            P[i, j] = sum(a[k] * M[k + 1][i, j] for k in range(len(a)))
+    return mu + rho * P / Q
+
+
+@pytest.mark.parametrize("r,N,sigma", [(2, 1, 60.0), (3, 3, 60.0), (4, 6, 80.0), (2, 10, 60.0)])
+def test_poly_monomial_moving_sum_evaluation(oracle, r, N, sigma):
+    f = wl.smooth_image(30, 41, seed=2)
+    ref = _monomial_shiftable(f, r, sigma, N)
+    out = oracle.bilateral_poly(f, r, sigma, N)
+    assert np.max(np.abs(out - ref)) <= 1e-9 * T
+
+
+def test_poly_invariants(oracle):
+    rng = np.random.default_rng(16)
+    f = rng.uniform(0, 200, (13, 17))
+    base = oracle.bilateral_poly(f, 3, 30.0, 37)
+    # constant image, shift, scale (a = 2 exact in binary), transpose and flips
+    assert np.max(np.abs(oracle.bilateral_poly(np.full((9, 8), 77.0), 2, 30.0, 37) - 77.0)) < 1e-12
+    assert np.max(np.abs(oracle.bilateral_poly(f + 40.0, 3, 30.0, 37) - (base + 40.0))) < 1e-10
+    assert np.max(np.abs(oracle.bilateral_poly(2.0 * f, 3, 60.0, 37) - 2.0 * base)) < 1e-11
+    assert np.max(np.abs(oracle.bilateral_poly(np.ascontiguousarray(f.T), 3, 30.0, 37) - base.T)) < 1e-11
+    assert np.max(np.abs(oracle.bilateral_poly(np.ascontiguousarray(f[::-1]), 3, 30.0, 37) - base[::-1])) < 1e-11
+    # N >= N_p on data in [0, T]: a convex combination of the window
+    g = wl.random_image(20, 23, 8)
+    out = oracle.bilateral_poly(g, 4, 20.0, oracle.poly_order_for(20.0, T))
+    from numpy.lib.stride_tricks import sliding_window_view
+    mn = sliding_window_view(np.pad(g.astype(np.float64), 4, constant_values=np.inf), (9, 9)).min(axis=(-1, -2))
+    mx = sliding_window_view(np.pad(g.astype(np.float64), 4, constant_values=-np.inf), (9, 9)).max(axis=(-1, -2))
+    assert np.all(out >= mn - 1e-12) and np.all(out <= mx + 1e-12)
+
+
+def test_poly_two_level_closed_form(oracle):
+    """Two levels a | b: (n_a a + n_b b phi(b-a)) / (n_a + n_b phi(b-a)) with phi exact."""
+    H, W, split, r = 9, 11, 4, 2
+    a, b, sigma, N = 60.0, 100.0, 30, 37
+    f = np.full((H, W), a)
+    f[:, split:] = b
+    out = oracle.bilateral_poly(f, r, float(sigma), N)
+    phi = float(_poly_exact(b - a, sigma, N))
+    for i in range(H):
+        for j in range(W):
+            rows = min(H - 1, i + r) - max(0, i - r) + 1
+            c0, c1 = max(0, j - r), min(W - 1, j + r)
+            na = rows * max(0, min(c1, split - 1) - c0 + 1)
+            nb = rows * max(0, c1 - max(c0, split) + 1)
+            if f[i, j] == a:
+                expect = (na * a + nb * b * phi) / (na + nb * phi)
+            else:
+                expect = (nb * b + na * a * phi) / (nb + na * phi)
+            assert abs(out[i, j] - expect) < 1e-12
+
+
+def test_poly_gaussian_bilateral_limit(oracle):
+    """As N grows the filter approaches the Gaussian-range bilateral (eq. (5)), here by
+    direct NumPy window sums; the gap shrinks about in proportion to 1/N."""
+    f = wl.smooth_image(24, 28, seed=5).astype(np.float64)
+    r, sigma = 3, 30.0
+    H, W = f.shape
+    g = np.empty_like(f)
+    for i in range(H):
+        for j in range(W):
+            w = f[max(0, i - r):i + r + 1, max(0, j - r):j + r + 1]
+            k = np.exp(-((w - f[i, j]) ** 2) / (2 * sigma * sigma))
+            g[i, j] = (k * w).sum() / k.sum()
+    gaps = [np.max(np.abs(oracle.bilateral_poly(f, r, sigma, N) - g)) for N in (40, 80, 160)]
+    assert gaps[2] < 0.1
+    assert 1.6 < gaps[0] / gaps[1] < 2.4 and 1.6 < gaps[1] / gaps[2] < 2.4
+
+
+def test_poly_sampled_matches_full(oracle):
+    f = wl.rect_image(40, 50, seed=7)
+    full = oracle.bilateral_poly(f, 5, 30.0, 37)
+    idx = np.array([0, 49, 50 * 39, 40 * 50 - 1, 777, 1234, 1500])
+    assert np.array_equal(oracle.bilateral_poly_at(f, idx, 5, 30.0, 37), full.ravel()[idx])
