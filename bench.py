@@ -92,10 +92,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
-    ap.add_argument("--kernel-only", nargs="?", const="headline", default=None, choices=["headline", "spatial"],
-                    help="profiling mode: run the headline forward (or the spatial-kernel forward at the "
-                         "same size) --steps times after --warmup, and a device copy of --copy-mib MiB; "
-                         "print nothing but a summary line")
+    ap.add_argument("--kernel-only", nargs="?", const="headline", default=None,
+                    choices=["headline", "spatial", "poly", "poly_trunc"],
+                    help="profiling mode: run the headline forward (or the spatial-kernel or polynomial-"
+                         "kernel forward at the same size) --steps times after --warmup, and a device copy "
+                         "of --copy-mib MiB; print nothing but a summary line")
     ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -105,7 +106,7 @@ def main():
 
     import torch
     from paper_1107_4617_amd import (bilateral, bilateral_backward, bilateral_batched, bilateral_train,
-                                     plan_info, spatial_filter, spatial_sigma_for)
+                                     plan_info, poly_order_for, poly_plan_info, spatial_filter, spatial_sigma_for)
     from paper_1107_4617_amd import workloads as wl
 
     dev = torch.device("cuda:0")
@@ -123,9 +124,17 @@ def main():
     # the separable q_2 spatial kernel over the same window (Algorithm 2 with M = 9)
     sig_s = spatial_sigma_for(radius, 2)
     fwd_sp = lambda: bilateral(img, radius, sigma, T, N=N, out=out, spatial_sigma=sig_s, spatial_N=2)  # noqa: E731
+    # the polynomial range kernel (Section 3's p_N, eq. (5) scaling) at the same sigma_r:
+    # N_p = ceil(T^2 / (2 sigma_r^2)) = 37, all 75 Chebyshev coefficients or those above 1e-7
+    fwd_poly = lambda: bilateral(img, radius, sigma, T, out=out, range_kernel="poly")  # noqa: E731
+    fwd_poly_t = lambda: bilateral(img, radius, sigma, T, out=out, range_kernel="poly", weight_eps=1e-7)  # noqa: E731
     if args.kernel_only:
         if args.kernel_only == "spatial":
             fwd = fwd_sp
+        elif args.kernel_only == "poly":
+            fwd = fwd_poly
+        elif args.kernel_only == "poly_trunc":
+            fwd = fwd_poly_t
         # a plain device copy of known size: reference for the HBM byte counters
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, device=dev)
@@ -205,6 +214,15 @@ def main():
                                                       "spatial_sigma": sig_s, "spatial_N": 2,
                                                       "vs_box": round(mean_ms / ms_sp, 3)}
         variants["algorithm1_q2_rect4096_r20"] = {"Mpixel/s": round(px / ms_a1 / 1e3, 2), "ms": round(ms_a1, 4)}
+        log("timing polynomial range kernel")
+        n_p = poly_order_for(sigma, T)
+        for name, fn, eps_p in (("poly_pN37_rect4096_r20_s30", fwd_poly, 0.0),
+                                ("poly_pN37_trunc1e-7_rect4096_r20_s30", fwd_poly_t, 1e-7)):
+            ms_pl, _, _ = time_calls(fn, args.steps, args.warmup, stream)
+            kp, bp = poly_plan_info(sigma, T, eps=eps_p)
+            variants[name] = {"Mpixel/s": round(px / ms_pl / 1e3, 2), "ms": round(ms_pl, 4), "N": n_p,
+                              "chebyshev_coefficients": kp, "dropped_bound": bp,
+                              "vs_raised_cosine": round(mean_ms / ms_pl, 3)}
         # the paper's timed instance: 512x512, T = 5 (11x11 window), M x N = 3^2 x 5, i.e. the
         # spatial q_2 on [-5, 5] and the range q_4 on [-255, 255] (sigma_r = 255 / pi)
         small = torch.from_numpy(wl.smooth_image(512, 512, seed=1)).to(dev)

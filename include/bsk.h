@@ -68,7 +68,14 @@ typedef enum {
     BSK_I16 = 4     /* precision form: stack quantised to 16-bit fixed point (Q15), FP32 sums */
 } bsk_precision;
 
+/* Range kernel (Section 3): the raised cosine q_N (default) or the polynomial p_N. */
+typedef enum {
+    BSK_RANGE_COS = 0,   /* phi(t) = cos^N(t / (sigma_r sqrt N)), eq. (6) scaling */
+    BSK_RANGE_POLY = 1   /* phi(t) = (1 - t^2 / (2 N sigma_r^2))^N, eq. (5) scaling */
+} bsk_range_kernel;
+
 #define BSK_MAX_ORDERS 256     /* folded orders after truncation: N <= 511 untruncated */
+#define BSK_MAX_POLY_ORDER 4096 /* largest N of the polynomial range kernel */
 #define BSK_MAX_RADIUS 500     /* clamped radius limit of the fused kernels */
 
 /* Options; a zero-initialised struct means: automatic N_0, FP32, no
@@ -100,6 +107,22 @@ typedef struct {
      * 256- or 512-lane strips; the other entry points return BSK_EUNSUPPORTED. */
     int spatial_N;
     double spatial_sigma; /* > 0 when spatial_N != 0 */
+    /* Range kernel (bsk_range_kernel).  BSK_RANGE_POLY selects Section 3's
+     * p_N in the scaling of eq. (5): phi(t) = (1 - t^2 / (2 N sigma_r^2))^N,
+     * which tends to exp(-t^2 / 2 sigma_r^2) like the raised cosine.  Its
+     * automatic order (order_mode 0) is N_p = ceil(T^2 / (2 sigma_r^2)), the
+     * smallest keeping it non-negative and unimodal on [-T, T]; N is at most
+     * BSK_MAX_POLY_ORDER.  The filter is computed from box sums of the
+     * Chebyshev polynomials T_k of the values normalised to [-1, 1] (a
+     * polynomial basis, hence exact up to rounding); weight_eps > 0 drops the
+     * coefficients of the kernel's Chebyshev expansion past the point where
+     * their largest magnitudes sum to at most weight_eps (bsk_poly_plan_info).
+     * Supported: bilateral_shiftable_ex with BSK_FP32 or BSK_FP64, the box
+     * spatial kernel, no compensation; other requests return
+     * BSK_EUNSUPPORTED.  Precondition: the values each workgroup reads (its
+     * strip of columns and rows within r of its output rows) span at most T;
+     * beyond it the channels grow without bound. */
+    int range_kernel;
 } bsk_options;
 
 /*
@@ -193,6 +216,17 @@ int bsk_plan_info(int N, double eps, int *K, double *dropped);
 
 /* Dropped unfolded weight mass sum_{w_n < eps} w_n (0 if nothing dropped). */
 double bsk_truncation_error(int N, double eps);
+
+/* N_p = ceil(T^2 / (2 sigma_r^2)) for the polynomial range kernel; -1 on
+ * invalid input. */
+int bsk_poly_order_for(float sigma_r, float T);
+
+/* Plan of the polynomial range kernel of order N (N < 0: N_p) for sigma_r, T
+ * and truncation eps: the number of Chebyshev coefficients kept (the filter
+ * box-sums one more channel than that) and the bound on the dropped part of
+ * the normalised kernel, sum over dropped k of max_c |d_k(c)| (0 when eps is
+ * 0).  coefs and bound may be NULL.  Returns BSK_OK, BSK_EINVAL or BSK_ERANGE. */
+int bsk_poly_plan_info(int N, float sigma_r, float T, double eps, int *coefs, double *bound);
 
 /*
  * Launch-shape autotuner.  Times the candidate shapes (lanes per workgroup in

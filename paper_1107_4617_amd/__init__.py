@@ -3,12 +3,13 @@
 K. N. Chaudhury, "Constant-time filtering using shiftable kernels": Algorithm 2
 with a box spatial window (or the separable raised-cosine spatial kernel, and
 Algorithm 1 as its range-free case) and the raised-cosine range kernel
-cos^N(t / (sigma_r sqrt N)), computed by fused HIP kernels (libbsk.so) behind a
+cos^N(t / (sigma_r sqrt N)) or the polynomial one (1 - t^2 / (2 N sigma_r^2))^N, computed
+by fused HIP kernels (libbsk.so) behind a
 C ABI (include/bsk.h).  The torch-facing calls live in `filter`; importing this
 package does not touch the GPU.
 """
 from .filter import (BilateralFunction, ShiftableBilateral, autotune, bilateral, bilateral_backward,  # noqa: F401
-                     bilateral_batched, bilateral_train, order_for, plan_info, release, spatial_filter,
-                     spatial_sigma_for)
+                     bilateral_batched, bilateral_train, order_for, plan_info, poly_order_for, poly_plan_info,
+                     release, spatial_filter, spatial_sigma_for)
 
 __version__ = "0.1.0"

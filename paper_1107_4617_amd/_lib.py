@@ -20,6 +20,8 @@ BSK_EHIP = -4
 BSK_EUNSUPPORTED = -5
 
 BSK_FP32, BSK_BF16, BSK_FP16, BSK_FP64, BSK_I16 = 0, 1, 2, 3, 4
+BSK_RANGE_COS, BSK_RANGE_POLY = 0, 1
+RANGE_KERNELS = {"cos": BSK_RANGE_COS, "poly": BSK_RANGE_POLY}
 PRECISIONS = {"fp32": BSK_FP32, "bf16": BSK_BF16, "fp16": BSK_FP16, "fp64": BSK_FP64, "i16": BSK_I16}
 
 STATUS_NAMES = {0: "BSK_OK", -1: "BSK_EINVAL", -2: "BSK_ERANGE", -3: "BSK_ENOMEM", -4: "BSK_EHIP",
@@ -29,8 +31,8 @@ STATUS_NAMES = {0: "BSK_OK", -1: "BSK_EINVAL", -2: "BSK_ERANGE", -3: "BSK_ENOMEM
 EXPORTS = [
     "bilateral_shiftable", "bilateral_shiftable_ex", "bilateral_shiftable_train",
     "bilateral_shiftable_backward", "bilateral_shiftable_batched", "bilateral_shiftable_batched_graph",
-    "bsk_order_for", "bsk_plan_info", "bsk_truncation_error", "bsk_autotune", "bsk_last_error",
-    "bsk_release", "bsk_version",
+    "bsk_order_for", "bsk_plan_info", "bsk_truncation_error", "bsk_poly_order_for", "bsk_poly_plan_info",
+    "bsk_autotune", "bsk_last_error", "bsk_release", "bsk_version",
 ]
 
 
@@ -38,7 +40,8 @@ class Options(ctypes.Structure):
     _fields_ = [("order_mode", ctypes.c_int), ("N", ctypes.c_int), ("precision", ctypes.c_int),
                 ("weight_eps", ctypes.c_double), ("kahan", ctypes.c_int), ("pitch_in", ctypes.c_int),
                 ("pitch_out", ctypes.c_int), ("block", ctypes.c_int), ("strip_h", ctypes.c_int),
-                ("order_chunk", ctypes.c_int), ("spatial_N", ctypes.c_int), ("spatial_sigma", ctypes.c_double)]
+                ("order_chunk", ctypes.c_int), ("spatial_N", ctypes.c_int), ("spatial_sigma", ctypes.c_double),
+                ("range_kernel", ctypes.c_int)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -81,6 +84,8 @@ def load():
         "bsk_order_for": (_i, [_f, _f]),
         "bsk_plan_info": (_i, [_i, _d, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
         "bsk_truncation_error": (_d, [_i, _d]),
+        "bsk_poly_order_for": (_i, [_f, _f]),
+        "bsk_poly_plan_info": (_i, [_i, _f, _f, _d, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
         "bsk_autotune": (_i, [_vp, _i, _i, _i, _f, _f, _vp, ctypes.POINTER(Options), ctypes.c_char_p, _vp,
                               ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d)]),
         "bsk_last_error": (ctypes.c_char_p, []),

@@ -110,12 +110,43 @@ int pick_chunk(int K, int full, int small)
     return cost(small) < cost(full) ? small : full;
 }
 
+std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, double eps)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, double, double, double>, std::shared_ptr<const bsk::PolyPlan>> cache;
+    const auto key = std::make_tuple(N, sigma_r, T, eps);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    auto p = std::make_shared<bsk::PolyPlan>();
+    if (bsk::make_poly_plan(N, sigma_r, T, eps, p.get()) != 0) return nullptr;
+    if (cache.size() > 64) cache.clear();
+    cache[key] = p;
+    return p;
+}
+
+// Channel pairs per pass of the polynomial kernel: the full pass or its half,
+// whichever has the lower estimated cost.  Per pixel a pass costs about 16
+// VALU instructions per channel (transforms, sums, scan, recombination), 7 per
+// coefficient step of the recurrence from d_2N down to the pass's first
+// channel, and 60 for its starts.
+static int pick_chunk_poly(int pairs, int N, int full)
+{
+    auto cost = [&](int kc) {
+        double c = 0.0;
+        for (int p0 = 0; p0 < pairs; p0 += kc) c += 2.0 * kc * 16.0 + 7.0 * std::max(0, 2 * N + 1 - 2 * p0) + 60.0;
+        return c;
+    };
+    return cost(full / 2) < cost(full) ? full / 2 : full;
+}
+
 // Workgroups per compute unit of the kernel a resolved request will launch.
 static int kernel_occupancy(const Resolved &r, int kind)
 {
     static std::mutex mu;
     static std::map<std::tuple<int, int, int, int, int, int, int>, int> cache;
-    const auto key = std::make_tuple(kind, r.block, r.kc, r.prec, r.kahan, r.sp.nsc * 2 + (r.sp.even ? 1 : 0), [] {
+    const auto key = std::make_tuple(kind + 3 * r.range_kernel, r.block, r.kc, r.prec, r.kahan,
+                                     r.sp.nsc * 2 + (r.sp.even ? 1 : 0), [] {
         int d = 0;
         (void)hipGetDevice(&d);
         return d;
@@ -128,7 +159,12 @@ static int kernel_occupancy(const Resolved &r, int kind)
     bsk::StripArgs a;
     std::memset(&a, 0, sizeof(a));
     int occ = 1;
-    if (r.sp.Ns > 0) {
+    if (r.range_kernel == BSK_RANGE_POLY) {
+        bsk::PolyArgs pa;
+        std::memset(&pa, 0, sizeof(pa));
+        if (r.prec == BSK_FP64) (void)bsk::launch_poly_f64(pa, r.block, nullptr, &occ);
+        else (void)bsk::launch_poly_f32(pa, r.block, r.kc, nullptr, &occ);
+    } else if (r.sp.Ns > 0) {
         (void)bsk::launch_spatial_f32(a, r.block, r.sp, r.kc, nullptr, &occ);
     } else if (kind == kTrain) {
         (void)bsk::launch_train_f32(a, r.block, nullptr, &occ);
@@ -167,17 +203,44 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     const long long nmax = (long long)H * (long long)W;
     if (nmax > (1LL << 40)) return fail(BSK_EINVAL, "image too large");
 
-    if (o.order_mode == 1) {
-        r->N = o.N;
+    if (o.range_kernel != BSK_RANGE_COS && o.range_kernel != BSK_RANGE_POLY)
+        return fail(BSK_EINVAL, "unknown range_kernel %d", o.range_kernel);
+    r->range_kernel = o.range_kernel;
+    const bool poly = o.range_kernel == BSK_RANGE_POLY;
+    r->poly.reset();
+    r->poly_pairs = 0;
+    if (poly) {
+        if (kind != kForward) return fail(BSK_EUNSUPPORTED, "the polynomial range kernel has the forward filter only");
+        if (o.spatial_N != 0) return fail(BSK_EUNSUPPORTED, "the polynomial range kernel uses the box spatial kernel");
+        if ((r->prec != BSK_FP32 && r->prec != BSK_FP64) || r->kahan)
+            return fail(BSK_EUNSUPPORTED, "the polynomial range kernel runs in FP32 or FP64 without compensation");
+        if (o.order_mode == 1) {
+            r->N = o.N;
+        } else {
+            const double x = (double)T / (double)sigma_r;
+            if (!(0.5 * x * x <= (double)bsk::kMaxPolyOrder))
+                return fail(BSK_ERANGE, "automatic polynomial order exceeds %d", bsk::kMaxPolyOrder);
+            r->N = bsk::poly_order_for(sigma_r, T);
+        }
+        if (r->N > bsk::kMaxPolyOrder)
+            return fail(BSK_ERANGE, "polynomial order N=%d exceeds %d", r->N, bsk::kMaxPolyOrder);
+        r->poly = poly_plan(r->N, sigma_r, T, o.weight_eps);
+        if (!r->poly) return fail(BSK_EINVAL, "bad polynomial kernel plan");
+        r->poly_pairs = (r->poly->K + 2) / 2;
+        r->plan = bsk::Plan();
     } else {
-        const double x = 2.0 * (double)T / (M_PI * (double)sigma_r);
-        if (!(x * x < 1e7)) return fail(BSK_ERANGE, "automatic order N_0 too large");
-        r->N = bsk::order_for(sigma_r, T);
+        if (o.order_mode == 1) {
+            r->N = o.N;
+        } else {
+            const double x = 2.0 * (double)T / (M_PI * (double)sigma_r);
+            if (!(x * x < 1e7)) return fail(BSK_ERANGE, "automatic order N_0 too large");
+            r->N = bsk::order_for(sigma_r, T);
+        }
+        if (r->N > 1000000) return fail(BSK_ERANGE, "order N=%d too large", r->N);
+        if (bsk::make_plan(r->N, sigma_r, o.weight_eps, &r->plan) != 0)
+            return fail(BSK_ERANGE, "order N=%d leaves more than %d folded orders (raise weight_eps)", r->N,
+                        bsk::kMaxOrders);
     }
-    if (r->N > 1000000) return fail(BSK_ERANGE, "order N=%d too large", r->N);
-    if (bsk::make_plan(r->N, sigma_r, o.weight_eps, &r->plan) != 0)
-        return fail(BSK_ERANGE, "order N=%d leaves more than %d folded orders (raise weight_eps)", r->N,
-                    bsk::kMaxOrders);
 
     // Clamping the radius to the image leaves every truncated window unchanged
     // (offsets beyond the image never occur, so no spatial weight changes).
@@ -208,7 +271,7 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
 
     int block = o.block;
     int tuned_S = 0, tuned_kc = 0;
-    if (kind == kForward && !spatial && o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
+    if (kind == kForward && !spatial && !poly && o.block == 0 && o.strip_h == 0 && o.order_chunk == 0) {
         int tb = 0, ts = 0, tk = 0;
         if (tuned_shape(r->rh, r->plan.K, H, W, r->prec, &tb, &ts, &tk)) {
             block = tb;
@@ -239,7 +302,21 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     r->block = block;
     if (o.order_chunk < 0) return fail(BSK_EINVAL, "order_chunk must be >= 0");
     int kc = o.order_chunk ? o.order_chunk : tuned_kc;
-    if (spatial) {
+    if (poly) {
+        if (r->prec == BSK_FP64) {
+            kc = bsk::chunk_poly_f64(block);
+        } else {
+            const int full = bsk::chunk_poly_f32(block);
+            if (o.order_chunk) {
+                if (o.order_chunk != full && o.order_chunk != full / 2)
+                    return fail(BSK_EINVAL, "order_chunk %d is not a polynomial-kernel pass size (%d or %d)",
+                                o.order_chunk, full, full / 2);
+                kc = o.order_chunk;
+            } else {
+                kc = pick_chunk_poly(r->poly_pairs, r->N, full);
+            }
+        }
+    } else if (spatial) {
         const int full = bsk::chunk_spatial_f32(block, r->sp.nsc);
         const int small = bsk::chunk_spatial_small_f32(block, r->sp.nsc);
         if (o.order_chunk) {
@@ -331,6 +408,90 @@ using namespace bsk::host;
 
 namespace {
 
+// Coefficient tables of the polynomial kernel, uploaded to a workspace slot
+// of the stream when the plan or the buffer changes.
+struct PolyUpload {
+    const bsk::PolyPlan *plan = nullptr;
+    std::shared_ptr<const bsk::PolyPlan> keep;   // keeps the plan (and so the key) alive
+    int np = 0;
+    int prec = -1;
+    void *ptr = nullptr;
+    std::vector<unsigned char> host;
+};
+std::mutex g_poly_mu;
+std::map<std::pair<int, void *>, PolyUpload> g_poly_up;
+
+int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, void *stream)
+{
+    const bsk::PolyPlan &pp = *r.poly;
+    const int kc = r.kc;
+    const int np = (r.poly_pairs + kc - 1) / kc * kc;
+    const bool f64 = r.prec == BSK_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    const size_t nrows = (size_t)(2 * std::max(pp.N, np) + 3) * bsk::kPolyRow;
+    const size_t nsig = (size_t)(2 * np + 2);
+    void *tab = nullptr;
+    int st = get_ws(stream, 6, (nrows + nsig) * esz, &tab);
+    if (st) return st;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    {
+        std::lock_guard<std::mutex> lk(g_poly_mu);
+        PolyUpload &u = g_poly_up[std::make_pair(dev, stream)];
+        if (u.plan != &pp || u.np != np || u.prec != r.prec || u.ptr != tab) {
+            if (!u.host.empty()) {
+                // an earlier upload from the host copy may still be pending on the stream
+                e = hipStreamSynchronize((hipStream_t)stream);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            }
+            u.host.assign((nrows + nsig) * esz, 0);
+            auto put = [&](size_t i, double v) {
+                if (f64) ((double *)u.host.data())[i] = v;
+                else ((float *)u.host.data())[i] = (float)v;
+            };
+            for (size_t i = 0; i < pp.rows.size(); ++i) put(i, pp.rows[i]);
+            // sig[0] belongs to e_{-1}, which is zero
+            for (size_t q = 1; q < nsig; ++q)
+                put(nrows + q, (int)q - 1 < pp.K ? std::exp(pp.lsig[q - 1] - pp.lsig[0]) : 0.0);
+            e = hipMemcpyAsync(tab, u.host.data(), u.host.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "coefficient table upload");
+            u.plan = &pp;
+            u.keep = r.poly;
+            u.np = np;
+            u.prec = r.prec;
+            u.ptr = tab;
+        }
+    }
+    bsk::PolyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.io.img = img;
+    a.io.out = out;
+    a.io.H = H;
+    a.io.W = W;
+    a.io.pitch_in = r.pitch_in;
+    a.io.pitch_out = r.pitch_out;
+    a.rh = r.rh;
+    a.rv = r.rv;
+    a.S = r.S;
+    a.NP = np;
+    a.N = pp.N;
+    a.rho = pp.rho;
+    a.inv_rho = 1.0 / pp.rho;
+    a.rows = tab;
+    a.sig = (const char *)tab + nrows * esz;
+    if (np > kc) {
+        void *ws = nullptr;
+        st = get_ws(stream, 0, 2 * (size_t)H * W * esz, &ws);
+        if (st) return st;
+        a.ws = ws;
+    }
+    e = f64 ? bsk::launch_poly_f64(a, r.block, (hipStream_t)stream)
+            : bsk::launch_poly_f32(a, r.block, kc, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "polynomial-kernel launch");
+    return BSK_OK;
+}
+
 int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
                  const bsk_options *opt, void *stream)
 {
@@ -341,6 +502,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
     const size_t esz = r.prec == BSK_FP64 ? 8 : 4;
     if (overlap(img, ((size_t)(H - 1) * r.pitch_in + W) * esz, out, ((size_t)(H - 1) * r.pitch_out + W) * esz))
         return fail(BSK_EINVAL, "img and out overlap");
+    if (r.range_kernel == BSK_RANGE_POLY) return poly_forward(img, H, W, r, out, stream);
     bsk::StripArgs a;
     const int kc = r.kc;
     fill_args(&a, r, H, W, kc);
@@ -510,6 +672,32 @@ double bsk_truncation_error(int N, double eps)
     return d;
 }
 
+int bsk_poly_order_for(float sigma_r, float T)
+{
+    if (!finite_pos(sigma_r) || !finite_pos(T)) return fail(-1, "sigma_r and T must be finite and > 0");
+    const double x = (double)T / (double)sigma_r;
+    if (!(0.5 * x * x < 2e9)) return fail(-1, "order too large");
+    return bsk::poly_order_for(sigma_r, T);
+}
+
+int bsk_poly_plan_info(int N, float sigma_r, float T, double eps, int *coefs, double *bound)
+{
+    if (!finite_pos(sigma_r) || !finite_pos(T)) return fail(BSK_EINVAL, "sigma_r and T must be finite and > 0");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BSK_EINVAL, "eps must be finite and >= 0");
+    if (N < 0) {
+        const double x = (double)T / (double)sigma_r;
+        if (!(0.5 * x * x <= (double)bsk::kMaxPolyOrder))
+            return fail(BSK_ERANGE, "automatic polynomial order exceeds %d", bsk::kMaxPolyOrder);
+        N = bsk::poly_order_for(sigma_r, T);
+    }
+    if (N > bsk::kMaxPolyOrder) return fail(BSK_ERANGE, "polynomial order N=%d exceeds %d", N, bsk::kMaxPolyOrder);
+    auto p = poly_plan(N, sigma_r, T, eps);
+    if (!p) return fail(BSK_EINVAL, "bad polynomial kernel plan");
+    if (coefs) *coefs = p->K;
+    if (bound) *bound = p->bound;
+    return BSK_OK;
+}
+
 const char *bsk_last_error(void) { return g_err; }
 
 void bsk_release_batched(void);
@@ -529,6 +717,10 @@ int bsk_release(void)
         }
     }
     g_ws.clear();
+    {
+        std::lock_guard<std::mutex> lp(g_poly_mu);
+        g_poly_up.clear();
+    }
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     return BSK_OK;
 }

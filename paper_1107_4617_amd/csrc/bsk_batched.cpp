@@ -38,6 +38,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     if (opt) o = *opt;
     if (o.precision != BSK_FP32 || o.kahan) return fail(BSK_EUNSUPPORTED, "the batched path is FP32");
     if (o.spatial_N != 0) return fail(BSK_EUNSUPPORTED, "the batched path uses the box spatial kernel");
+    if (o.range_kernel != BSK_RANGE_COS) return fail(BSK_EUNSUPPORTED, "the batched path uses the raised cosine");
     if (o.pitch_in || o.pitch_out) return fail(BSK_EUNSUPPORTED, "the batched path needs dense pitch");
     if (o.strip_h < 0 || !(o.weight_eps >= 0.0)) return fail(BSK_EINVAL, "bad options");
 
@@ -474,6 +475,7 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     o.strip_h = 0;
     o.order_chunk = 0;
     if (o.spatial_N != 0) return fail(BSK_EUNSUPPORTED, "the autotuner covers the box spatial kernel");
+    if (o.range_kernel != BSK_RANGE_COS) return fail(BSK_EUNSUPPORTED, "the autotuner covers the raised cosine");
     Resolved base;
     int st = resolve(H, W, radius, sigma_r, T, &o, &base);
     if (st) return st;

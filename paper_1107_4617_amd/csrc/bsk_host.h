@@ -1,6 +1,8 @@
 // Host-side helpers shared by the C ABI translation units of libbsk.
 #pragma once
 
+#include <memory>
+
 #include "../../include/bsk.h"
 #include "bsk_internal.h"
 
@@ -24,8 +26,11 @@ struct Resolved {
     int block;
     int kc;        // orders per pass of the kernel the request runs
     int S;
-    bsk::Plan plan;
+    bsk::Plan plan;        // raised-cosine range kernel (unused for the polynomial one)
     bsk::SpatialPlan sp;   // Ns = 0: the box
+    int range_kernel;      // bsk_range_kernel
+    std::shared_ptr<const bsk::PolyPlan> poly;   // polynomial range kernel
+    int poly_pairs;        // channel pairs of the polynomial kernel, ceil((K + 1) / 2)
 };
 
 // The kernel family a request is resolved for: its pass sizes and residency
@@ -36,6 +41,8 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
 // Orders per pass from a kernel family's full pass and a smaller one (0: half
 // the full one): the one with the lower estimated cost for K orders.
 int pick_chunk(int K, int full, int small = 0);
+// Plan of the polynomial range kernel, cached per (N, sigma_r, T, eps).
+std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, double eps);
 // Fills the launch arguments; the weights are padded with zeros to a multiple
 // of `kc` (the pass size of the kernel that will run).
 void fill_args(bsk::StripArgs *a, const Resolved &r, int H, int W, int kc);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace bsk {
 
 constexpr int kMaxOrders = 256;   // folded orders a plan may keep
@@ -52,6 +54,42 @@ int order_for(double sigma_r, double T);
 // Full folded-order count and dropped mass without the kMaxOrders limit.
 void plan_counts(int N, double eps, int *K, double *dropped);
 
+// Plan of the polynomial range kernel (Section 3, p_N, in the scaling of
+// eq. (5)): phi(t) = (1 - t^2 / (2 N sigma_r^2))^N.  Values are mapped to
+// x = (f - mu) / rho with rho = T / 2 and mu the midrange of the data a
+// workgroup reads, so x lies in [-1, 1] when the data span at most T.  For a
+// centre value c the kernel is then g_c(x) = (1 - (x - c)^2 / a^2)^N with
+// a = sqrt(2N) sigma_r / rho, a polynomial of degree 2N in x, expanded in
+// Chebyshev polynomials: g_c = sum_k d_k(c) T_k(x).  The box sums of the
+// channels T_k(x) and x T_k(x) = (T_{k+1} + T_{k-1}) / 2 then give P and Q.
+// The coefficients d_k(c) satisfy a five-term recurrence in k (from the
+// differential equation h g' = N h' g of g = h^N), run downwards from the
+// leading coefficient d_2N in a scaled form d_k = s_k e_k, where s_k is the
+// largest |d_k(c)| over c in [-1, 1], so every scaled value stays near 1:
+//   e_{k-2} = c alpha_k e_{k-1} + (beta_k + gamma_k c^2) e_k
+//             + c delta_k e_{k+1} + epsilon_k e_{k+2} + kappa_k,
+// where the constant kappa is zero except in the step k = 2N + 2 that starts
+// the recurrence, e_2N = kappa = (-1)^N; the steps above it are all zero.
+struct PolyPlan {
+    int N = 0;
+    int K = 0;               // coefficients kept: d_k for k < K (channels 0 .. K are box-summed)
+    double rho = 0.0;        // half-width of the normalised interval (T / 2)
+    double ahat = 0.0;       // sqrt(2N) sigma_r / rho
+    double bound = 0.0;      // sum over the dropped k of max_c |d_k(c)|: bound on |g_c - kept part|
+    double top = 1.0;        // scaled leading coefficient e_2N = (-1)^N
+    std::vector<double> lsig;   // ln s_k, k = 0 .. 2N
+    // kPolyRow values per k = 0 .. 2N + 2: (alpha, beta, gamma, delta, epsilon, kappa) of
+    // the step that yields e_{k-2}; rows 0 and 1 are zero (e_{-1} = 0 where a pass needs it)
+    std::vector<double> rows;
+};
+constexpr int kPolyRow = 8;
+constexpr int kMaxPolyOrder = 4096;
+// Returns 0, or -1 for N < 0 or N > kMaxPolyOrder or a bad sigma_r / T.
+int make_poly_plan(int N, double sigma_r, double T, double eps, PolyPlan *pp);
+// Smallest N with the polynomial kernel non-negative and unimodal on [-T, T]:
+// ceil(T^2 / (2 sigma_r^2)).
+int poly_order_for(double sigma_r, double T);
+
 // Buffers and layout of one image as the kernel policies see them.
 struct IO {
     const void *img;       // f, float or double, pitch_in elements per row
@@ -86,6 +124,23 @@ struct StripArgs {
     const float *sp_row;   // (cos, sin)(nu_j y), j-major, H rows
     const float *sp_col;   // (cos, sin)(nu_j x), j-major, W columns
 };
+
+// Per-launch arguments of the polynomial-kernel strip kernel.
+struct PolyArgs {
+    IO io;
+    void *ws;              // partial accumulators (2 planes) across passes, or null
+    int rh, rv, S;
+    int NP;                // channel pairs, padded to a multiple of the pass size
+    int N;
+    double rho, inv_rho;   // interval half-width and its inverse
+    const void *rows;      // kPolyRow coefficients per k = 0 .. 2 max(N, NP) + 2 (float or
+                           // double), zero past the plan's rows
+    const void *sig;       // 0, then s_k / s_0 for k < K, then zero: 2 NP + 2 entries
+};
+hipError_t launch_poly_f32(const PolyArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
+hipError_t launch_poly_f64(const PolyArgs &a, int block, hipStream_t s, int *occ = nullptr);
+int chunk_poly_f32(int block);   // pairs per full pass (the half pass has half)
+int chunk_poly_f64(int block);
 
 // Launch helpers implemented in bsk_kernels.hip.  `prec` selects the stack
 // quantisation (bsk_precision) for the FP32 kernels.  With occ non-null a

@@ -15,8 +15,8 @@ import torch
 from . import _lib
 
 __all__ = ["bilateral", "spatial_filter", "spatial_sigma_for", "bilateral_train", "bilateral_backward",
-           "bilateral_batched", "order_for", "plan_info", "autotune", "BilateralFunction", "ShiftableBilateral",
-           "release"]
+           "bilateral_batched", "order_for", "plan_info", "poly_order_for", "poly_plan_info", "autotune",
+           "BilateralFunction", "ShiftableBilateral", "release"]
 
 
 def _stream():
@@ -37,8 +37,11 @@ def _check_image(t: torch.Tensor, name: str, dtype=torch.float32):
 
 
 def _options(N=None, precision="fp32", weight_eps=0.0, kahan=False, block=0, strip_h=0, order_chunk=0,
-             spatial_sigma=None, spatial_N=None):
+             spatial_sigma=None, spatial_N=None, range_kernel="cos"):
     o = _lib.Options()
+    if range_kernel not in _lib.RANGE_KERNELS:
+        raise ValueError(f"range_kernel must be one of {sorted(_lib.RANGE_KERNELS)}")
+    o.range_kernel = _lib.RANGE_KERNELS[range_kernel]
     if spatial_sigma is not None:
         o.spatial_sigma = float(spatial_sigma)
         o.spatial_N = -1 if spatial_N is None else int(spatial_N)
@@ -75,11 +78,36 @@ def plan_info(N: int, eps: float = 0.0):
     return K.value, d.value
 
 
+def poly_order_for(sigma_r: float, T: float = 255.0) -> int:
+    """N_p = ceil(T^2 / (2 sigma_r^2)): smallest order making the polynomial kernel
+    non-negative and unimodal on [-T, T]."""
+    n = _lib.load().bsk_poly_order_for(float(sigma_r), float(T))
+    if n < 0:
+        _lib.check(_lib.BSK_EINVAL)
+    return n
+
+
+def poly_plan_info(sigma_r: float, T: float = 255.0, N: Optional[int] = None, eps: float = 0.0):
+    """(Chebyshev coefficients kept, bound on the dropped part of the normalised kernel) of the
+    polynomial range kernel; the filter box-sums one channel more than the coefficients kept."""
+    K = ctypes.c_int(0)
+    b = ctypes.c_double(0.0)
+    _lib.check(_lib.load().bsk_poly_plan_info(-1 if N is None else int(N), float(sigma_r), float(T), float(eps),
+                                              ctypes.byref(K), ctypes.byref(b)))
+    return K.value, b.value
+
+
 def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,
               precision: str = "fp32", weight_eps: float = 0.0, kahan: bool = False, block: int = 0,
               strip_h: int = 0, order_chunk: int = 0, out: Optional[torch.Tensor] = None,
-              spatial_sigma: Optional[float] = None, spatial_N: Optional[int] = None) -> torch.Tensor:
+              spatial_sigma: Optional[float] = None, spatial_N: Optional[int] = None,
+              range_kernel: str = "cos") -> torch.Tensor:
     """Bilateral filter on the (2r+1)^2 window with the range kernel cos^N(t / (sigma_r sqrt N)).
+
+    range_kernel: "cos" (the raised cosine above) or "poly", the polynomial kernel
+    (1 - t^2 / (2 N sigma_r^2))^N (Section 3's p_N in the scaling of eq. (5); N None selects
+    N_p(sigma_r, T); precision "fp32" or "fp64"; weight_eps > 0 truncates its Chebyshev
+    expansion; box spatial kernel only).
 
     precision: "fp32" (default); "bf16", "fp16" or "i16" (precision form: the cos/sin stack
     quantised to bfloat16, float16 or 16-bit fixed point, FP32 sums); "fp64" (img float64).
@@ -98,7 +126,8 @@ def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, 
         if out.shape != img.shape:
             raise ValueError("out has the wrong shape")
     H, W = img.shape
-    opt = _options(N, precision, weight_eps, kahan, block, strip_h, order_chunk, spatial_sigma, spatial_N)
+    opt = _options(N, precision, weight_eps, kahan, block, strip_h, order_chunk, spatial_sigma, spatial_N,
+                   range_kernel)
     with torch.cuda.device(img.device):
         _lib.check(_lib.load().bilateral_shiftable_ex(
             ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),

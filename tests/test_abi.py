@@ -213,3 +213,85 @@ def test_spatial_kernel_errors(lib):
     d = (_lib.ImageDesc * 1)()
     d[0].img, d[0].out, d[0].H, d[0].W, d[0].radius, d[0].sigma_r, d[0].N = big, big2, 8, 8, 2, 30.0, -1
     assert lib.bilateral_shiftable_batched(d, 1, 255.0, ctypes.byref(o), None) == _lib.BSK_EUNSUPPORTED
+
+
+# ------------------------------------------------ polynomial range kernel ----
+@pytest.mark.parametrize("sigma,expect", [(30.0, 37), (60.0, 10), (15.0, 145), (255.0, 1)])
+def test_poly_order_for(lib, sigma, expect):
+    assert lib.bsk_poly_order_for(sigma, 255.0) == expect
+    assert lib.bsk_poly_order_for(0.0, 255.0) == -1
+
+
+def _cheb_coef_max(N, sigma, T, grid=257):
+    """max over centres c in [-1, 1] of |d_k(c)|, the Chebyshev coefficients of
+    (1 - (x - c)^2 / a^2)^N, a = sqrt(2N) sigma / (T / 2), by repeated series products."""
+    from numpy.polynomial import chebyshev as C
+    a2 = 2.0 * N * (sigma / (0.5 * T)) ** 2
+    best = np.zeros(2 * N + 1)
+    for c in np.linspace(-1.0, 1.0, grid):
+        h = np.array([1.0 - (c * c + 0.5) / a2, 2.0 * c / a2, -0.5 / a2])   # h in the T_k basis
+        d = np.array([1.0])
+        for _ in range(N):
+            d = C.chebmul(d, h)
+        best = np.maximum(best, np.abs(d))
+    return best
+
+
+@pytest.mark.parametrize("N,sigma,eps", [(37, 30.0, 1e-7), (10, 60.0, 1e-7), (37, 30.0, 1e-4), (60, 30.0, 1e-7),
+                                         (5, 100.0, 0.0)])
+def test_poly_plan_truncation(lib, N, sigma, eps):
+    """Kept coefficient count and dropped bound against an independent FP64 expansion (series
+    products, not the library's recurrence)."""
+    K = ctypes.c_int(0)
+    b = ctypes.c_double(0.0)
+    assert lib.bsk_poly_plan_info(N, sigma, 255.0, eps, ctypes.byref(K), ctypes.byref(b)) == _lib.BSK_OK
+    mx = _cheb_coef_max(N, sigma, 255.0)
+    if eps == 0.0:
+        assert K.value == 2 * N + 1 and b.value == 0.0
+        return
+    tail = mx[K.value:].sum()
+    assert tail <= eps * (1 + 1e-6)
+    assert mx[K.value - 1:].sum() > eps * (1 - 1e-6)
+    assert abs(b.value - tail) <= 1e-6 * eps
+
+
+def test_poly_plan_info_errors(lib):
+    K = ctypes.c_int(0)
+    b = ctypes.c_double(0.0)
+    assert lib.bsk_poly_plan_info(5000, 30.0, 255.0, 0.0, ctypes.byref(K), ctypes.byref(b)) == _lib.BSK_ERANGE
+    assert lib.bsk_poly_plan_info(-1, 2.0, 255.0, 0.0, ctypes.byref(K), ctypes.byref(b)) == _lib.BSK_ERANGE
+    assert lib.bsk_poly_plan_info(10, -1.0, 255.0, 0.0, None, None) == _lib.BSK_EINVAL
+    assert lib.bsk_poly_plan_info(10, 30.0, 255.0, -1.0, None, None) == _lib.BSK_EINVAL
+    assert lib.bsk_poly_plan_info(0, 30.0, 255.0, 0.0, ctypes.byref(K), None) == _lib.BSK_OK and K.value == 1
+
+
+def test_poly_kernel_errors(lib):
+    """Requests the polynomial range kernel does not run are refused before any launch."""
+    big, big2 = 1 << 40, 1 << 41
+
+    def opt(**kw):
+        o = _lib.Options()
+        o.range_kernel = _lib.BSK_RANGE_POLY
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    bad = _lib.Options()
+    bad.range_kernel = 7
+    assert _call_ex(lib, img=big, out=big2, opt=bad) == _lib.BSK_EINVAL
+    assert _call_ex(lib, img=big, out=big2, opt=opt(precision=_lib.BSK_BF16)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(precision=_lib.BSK_I16)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(kahan=1)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(spatial_N=2, spatial_sigma=2.0)) == _lib.BSK_EUNSUPPORTED
+    assert _call_ex(lib, img=big, out=big2, opt=opt(order_mode=1, N=4097)) == _lib.BSK_ERANGE
+    assert _call_ex(lib, img=big, out=big2, s=2.0, opt=opt()) == _lib.BSK_ERANGE     # N_p = 8129
+    assert _call_ex(lib, img=big, out=big2, opt=opt(order_chunk=5)) == _lib.BSK_EINVAL
+    vp = ctypes.c_void_p
+    o = opt()
+    assert lib.bilateral_shiftable_train(vp(big), 8, 8, 2, 30.0, 255.0, ctypes.byref(o), vp(big2), vp(1 << 42),
+                                         None) == _lib.BSK_EUNSUPPORTED
+    assert lib.bilateral_shiftable_backward(vp(big), vp(big2), None, None, 8, 8, 2, 30.0, 255.0, ctypes.byref(o),
+                                            vp(1 << 43), None, None) == _lib.BSK_EUNSUPPORTED
+    d = (_lib.ImageDesc * 1)()
+    d[0].img, d[0].out, d[0].H, d[0].W, d[0].radius, d[0].sigma_r, d[0].N = big, big2, 8, 8, 2, 30.0, -1
+    assert lib.bilateral_shiftable_batched(d, 1, 255.0, ctypes.byref(o), None) == _lib.BSK_EUNSUPPORTED
