@@ -128,13 +128,17 @@ std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, 
 // Channel pairs per pass of the polynomial kernel: the full pass or its half,
 // whichever has the lower estimated cost.  Per pixel a pass costs about 16
 // VALU instructions per channel (transforms, sums, scan, recombination), 7 per
-// coefficient step of the recurrence from d_2N down to the pass's first
-// channel, and 60 for its starts.
+// step of the coefficient recurrence over its channels, 100 for its starts
+// and, when there are several passes, the equivalent of about 250 for the
+// workspace traffic (48 bytes per pixel); the first pass also runs the
+// recurrence from d_2N down to its channels.
 static int pick_chunk_poly(int pairs, int N, int full)
 {
     auto cost = [&](int kc) {
-        double c = 0.0;
-        for (int p0 = 0; p0 < pairs; p0 += kc) c += 2.0 * kc * 16.0 + 7.0 * std::max(0, 2 * N + 1 - 2 * p0) + 60.0;
+        const int np = (pairs + kc - 1) / kc * kc;
+        const int passes = np / kc;
+        double c = passes * (2.0 * kc * 16.0 + 7.0 * (2 * kc + 2) + 100.0 + (passes > 1 ? 250.0 : 0.0));
+        c += 7.0 * std::max(0, 2 * N - 2 * np);
         return c;
     };
     return cost(full / 2) < cost(full) ? full / 2 : full;
@@ -482,7 +486,7 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
     a.sig = (const char *)tab + nrows * esz;
     if (np > kc) {
         void *ws = nullptr;
-        st = get_ws(stream, 0, 2 * (size_t)H * W * esz, &ws);
+        st = get_ws(stream, 0, 6 * (size_t)H * W * esz, &ws);
         if (st) return st;
         a.ws = ws;
     }

@@ -128,7 +128,8 @@ struct StripArgs {
 // Per-launch arguments of the polynomial-kernel strip kernel.
 struct PolyArgs {
     IO io;
-    void *ws;              // partial accumulators (2 planes) across passes, or null
+    void *ws;              // across passes: accumulators Q, 2P and four recurrence values
+                           // (6 planes of H*W), or null for a single pass
     int rh, rv, S;
     int NP;                // channel pairs, padded to a multiple of the pass size
     int N;

@@ -79,7 +79,9 @@ __device__ __forceinline__ AT poly_coef_step(ConstPtr<AT> row, AT c, AT c2, AT w
     return fmat(c * row[0], w1, rest);
 }
 
-template <typename AT, int BLOCK, int KR, int KL>
+// MULTI: more than one pass (the workspace carries the partial sums and the
+// recurrence between passes); a single pass compiles without that code.
+template <typename AT, int BLOCK, int KR, int KL, bool MULTI>
 __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT *lds)
 {
     constexpr int ROWS = 2 * KL;
@@ -162,10 +164,14 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
     const ConstPtr<AT> sig = (ConstPtr<AT>)pa.sig;
     const int n2 = 2 * pa.N;
 
-    for (int p0 = 0; p0 < pa.NP; p0 += KR) {
+    // Passes run from the highest channels down: the coefficient recurrence
+    // runs downwards too, so a pass continues it from the four values the pass
+    // before left in the workspace (planes 2 .. 5) instead of from d_2N.
+    AT *const ws = (AT *)pa.ws;
+    for (int p0 = MULTI ? pa.NP - KR : 0; p0 >= 0; p0 -= KR) {
         const int k0 = 2 * p0;   // first channel of the pass
-        const bool first = (p0 == 0);
-        const bool last = (p0 + KR >= pa.NP);
+        const bool top_pass = !MULTI || (p0 + KR >= pa.NP);   // first to run
+        const bool base = !MULTI || (p0 == 0);                 // last to run: channels 0 and 1
 
         AT V[KR][2];
 #pragma unroll
@@ -229,15 +235,24 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                         rc = fetch(colok, rowc(iR + 1));
                         // e_j for j from 2N down to k0 - 1; values above the
                         // register range only feed the recurrence
-                        AT w1 = AT(0), w2 = AT(0), w3 = AT(0), w4 = AT(0);
+                        const long o = (long)iR * W + jx;
                         const int jtop = k0 + 2 * KR;
+                        AT w1 = AT(0), w2 = AT(0), w3 = AT(0), w4 = AT(0);
+                        if (top_pass) {
 #pragma unroll 2
-                        for (int j = n2; j > jtop; --j) {
-                            const AT e = poly_coef_step(rows + (long)kPolyRow * (j + 2), c, c2, w1, w2, w3, w4);
-                            w4 = w3;
-                            w3 = w2;
-                            w2 = w1;
-                            w1 = e;
+                            for (int j = n2; j > jtop; --j) {
+                                const AT e = poly_coef_step(rows + (long)kPolyRow * (j + 2), c, c2, w1, w2, w3, w4);
+                                w4 = w3;
+                                w3 = w2;
+                                w2 = w1;
+                                w1 = e;
+                            }
+                        } else {
+                            // e_{jtop+1} .. e_{jtop+4}, from the pass above
+                            w1 = ws[2 * plane + o];
+                            w2 = ws[3 * plane + o];
+                            w3 = ws[4 * plane + o];
+                            w4 = ws[5 * plane + o];
                         }
                         const ConstPtr<AT> rp = rows + (long)kPolyRow * (k0 + 1);   // row of j = k0 - 1
 #pragma unroll
@@ -248,6 +263,13 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                             w3 = w2;
                             w2 = w1;
                             w1 = e;
+                        }
+                        if (!base) {
+                            // e_{k0+1} .. e_{k0+4} for the pass below
+                            ws[2 * plane + o] = dd[2];
+                            ws[3 * plane + o] = dd[3];
+                            ws[4 * plane + o] = dd[4];
+                            ws[5 * plane + o] = dd[5];
                         }
                         // d_k = s_k e_k (s_k = 0 past the kept coefficients and for k = -1)
                         const ConstPtr<AT> sp = sig + k0;
@@ -265,7 +287,7 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                         accQ = fmat(dd[2 * m + 1], Ba, fmat(dd[2 * m + 2], Bb, accQ));
                         accP = fmat(dd[2 * m] + dd[2 * m + 2], Ba, fmat(dd[2 * m + 1] + dd[2 * m + 3], Bb, accP));
                         // x T_0 = T_1 carries d_0 in full: 2P gains another d_0 Box[T_1]
-                        if (m == 0 && first) accP = fmat(dd[1], Bb, accP);
+                        if (m == 0 && base) accP = fmat(dd[1], Bb, accP);
                     }
                 }
 
@@ -315,15 +337,15 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                 // ---- row iR complete: continue or finish its accumulators
                 if (actR && sR == NSUB - 1 && outlane) {
                     const long o = (long)iR * W + jx;
-                    if (!first) {
-                        accQ += ((AT *)pa.ws)[o];
-                        accP += ((AT *)pa.ws)[plane + o];
+                    if (!top_pass) {
+                        accQ += ws[o];
+                        accP += ws[plane + o];
                     }
-                    if (last) {
+                    if (base) {
                         ((AT *)a.out)[(long)iR * a.pitch_out + jx] = mu + rho * (AT(0.5) * accP / accQ);
                     } else {
-                        ((AT *)pa.ws)[o] = accQ;
-                        ((AT *)pa.ws)[plane + o] = accP;
+                        ws[o] = accQ;
+                        ws[plane + o] = accP;
                     }
                 }
                 __syncthreads();
@@ -347,11 +369,11 @@ constexpr int poly_minb()
     return BLOCK == 1024 ? 1 : (poly_lds_occupancy(strip_lds_elems<2, KL, BLOCK>() * (int)sizeof(AT)) >= 3 ? 3 : 2);
 }
 
-template <typename AT, int BLOCK, int KR, int KL>
+template <typename AT, int BLOCK, int KR, int KL, bool MULTI>
 __global__ void __launch_bounds__(BLOCK, (poly_minb<AT, BLOCK, KL>())) poly_kernel(const PolyArgs a)
 {
     __shared__ __align__(16) AT lds[strip_lds_elems<2, KL, BLOCK>()];
-    poly_body<AT, BLOCK, KR, KL>(a, blockIdx.x, blockIdx.y, lds);
+    poly_body<AT, BLOCK, KR, KL, MULTI>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <typename AT, int BLOCK, int KR, int KL>
@@ -359,15 +381,18 @@ static hipError_t poly_launch(const PolyArgs &a, hipStream_t s, int *occ)
 {
     if (occ) {
         int n = 0;
-        const hipError_t e =
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)poly_kernel<AT, BLOCK, KR, KL>, BLOCK, 0);
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, (const void *)poly_kernel<AT, BLOCK, KR, KL, true>, BLOCK, 0);
         *occ = (e == hipSuccess && n > 0) ? n : 1;
         return e;
     }
     const int Wt = BLOCK - 2 * a.rh;
-    if (Wt < 1 || a.S < 1 || a.NP % KR != 0) return hipErrorInvalidValue;
+    if (Wt < 1 || a.S < 1 || a.NP < KR || a.NP % KR != 0) return hipErrorInvalidValue;
+    const bool multi = a.NP > KR;
+    if (multi && !a.ws) return hipErrorInvalidValue;
     dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
-    hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL>), grid, dim3(BLOCK), 0, s, a);
+    if (multi) hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, true>), grid, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, false>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
