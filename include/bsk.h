@@ -15,7 +15,10 @@
  * the Gaussian exp(-t^2 / 2 sigma_r^2).  Being a finite sum of N+1 complex
  * exponentials (Section 1), phi is shiftable, so Algorithm 2 computes the
  * filter exactly (up to rounding) from O(1)-per-pixel moving sums
- * (Section 2, Sum(F, x, T)) of pointwise transforms of f.
+ * (Section 2, Sum(F, x, T)) of pointwise transforms of f.  bsk_options can
+ * select instead Section 3's polynomial kernel p_N in the scaling of eq. (5),
+ * (1 - t^2 / (2 N sigma_r^2))^N, also exact up to rounding (polynomials are
+ * shiftable).
  *
  * T is the range bound of Section 3 (values are assumed to span at most T).
  * It only selects the automatic order N_0 = ceil((2T / (pi sigma_r))^2), the

@@ -6,9 +6,10 @@
 // polynomials T_k of the normalised value x = (f - mu) / rho (rho = T / 2,
 // mu the midrange of the data the workgroup reads), not the monomials f^k:
 // T_k(x) lies in [-1, 1] and the expansion of the kernel in it has
-// coefficients bounded by 2, whereas the monomial expansion of (x - c)^(2N)
-// cancels terms of size up to about 2^(2N) and is useless in FP32.  For a
-// centre value c,
+// coefficients bounded by 2 that decay fast enough to be truncated, whereas
+// the monomial coefficients of (1 - (x - c)^2 / a^2)^N grow geometrically
+// with N (hundreds at N = 37, about 1e7 at N = 82, 1e13 at N = 145) and
+// cancel against each other in the sums.  For a centre value c,
 //     g_c(x) = phi(rho (x - c)) = sum_k d_k(c) T_k(x)
 //     Q(x0) = sum_k d_k(c) Box[T_k](x0)
 //     P(x0) = sum_k d_k(c) Box[x T_k](x0),  x T_k = (T_{k+1} + T_{k-1}) / 2,  x T_0 = T_1
