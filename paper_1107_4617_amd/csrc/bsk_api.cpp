@@ -455,6 +455,8 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
                 else ((float *)u.host.data())[i] = (float)v;
             };
             for (size_t i = 0; i < pp.rows.size(); ++i) put(i, pp.rows[i]);
+            // rows above the start shift the window by four
+            for (size_t i = pp.rows.size(); i < nrows; i += bsk::kPolyRow) put(i + 4, 1.0);
             // sig[0] belongs to e_{-1}, which is zero
             for (size_t q = 1; q < nsig; ++q)
                 put(nrows + q, (int)q - 1 < pp.K ? std::exp(pp.lsig[q - 1] - pp.lsig[0]) : 0.0);

@@ -67,9 +67,9 @@ void plan_counts(int N, double eps, int *K, double *dropped);
 // leading coefficient d_2N in a scaled form d_k = s_k e_k, where s_k is the
 // largest |d_k(c)| over c in [-1, 1], so every scaled value stays near 1:
 //   e_{k-2} = c alpha_k e_{k-1} + (beta_k + gamma_k c^2) e_k
-//             + c delta_k e_{k+1} + epsilon_k e_{k+2} + kappa_k,
-// where the constant kappa is zero except in the step k = 2N + 2 that starts
-// the recurrence, e_2N = kappa = (-1)^N; the steps above it are all zero.
+//             + c delta_k e_{k+1} + epsilon_k e_{k+2},
+// started by the row k = 2N + 2, whose only entry is epsilon = (-1)^N, from a
+// 1 placed at e_{2N+4}; rows above it shift by four (epsilon = 1).
 struct PolyPlan {
     int N = 0;
     int K = 0;               // coefficients kept: d_k for k < K (channels 0 .. K are box-summed)
@@ -78,8 +78,8 @@ struct PolyPlan {
     double bound = 0.0;      // sum over the dropped k of max_c |d_k(c)|: bound on |g_c - kept part|
     double top = 1.0;        // scaled leading coefficient e_2N = (-1)^N
     std::vector<double> lsig;   // ln s_k, k = 0 .. 2N
-    // kPolyRow values per k = 0 .. 2N + 2: (alpha, beta, gamma, delta, epsilon, kappa) of
-    // the step that yields e_{k-2}; rows 0 and 1 are zero (e_{-1} = 0 where a pass needs it)
+    // kPolyRow values per k = 0 .. 2N + 2: (alpha, beta, gamma, delta, epsilon) of the
+    // step that yields e_{k-2}; rows 0 and 1 are zero (e_{-1} = 0 where a pass needs it)
     std::vector<double> rows;
 };
 constexpr int kPolyRow = 8;
@@ -135,7 +135,7 @@ struct PolyArgs {
     int N;
     double rho, inv_rho;   // interval half-width and its inverse
     const void *rows;      // kPolyRow coefficients per k = 0 .. 2 max(N, NP) + 2 (float or
-                           // double), zero past the plan's rows
+                           // double); past the plan's rows only epsilon = 1 (a shift)
     const void *sig;       // 0, then s_k / s_0 for k < K, then zero: 2 NP + 2 entries
 };
 hipError_t launch_poly_f32(const PolyArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);

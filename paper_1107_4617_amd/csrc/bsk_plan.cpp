@@ -174,8 +174,9 @@ int make_poly_plan(int N, double sigma_r, double T, double eps, PolyPlan *pp)
     const int n2 = 2 * N;
     p.lsig.assign(n2 + 1, -std::numeric_limits<double>::infinity());
     p.rows.assign((size_t)(n2 + 3) * kPolyRow, 0.0);
-    // the step that yields e_2N has only its constant term: e_2N = top
-    p.rows[(size_t)(n2 + 2) * kPolyRow + 5] = p.top;
+    // the step that yields e_2N takes it from a 1 four places up: e_2N = top
+    // (the device shifts that 1 down with rows whose only entry is epsilon = 1)
+    p.rows[(size_t)(n2 + 2) * kPolyRow + 4] = p.top;
     if (N == 0) {
         // g = 1: d_0 = 1 and nothing to recur
         p.lsig[0] = 0.0;

@@ -68,16 +68,33 @@ struct ChebPair {
 template <typename AT>
 using ConstPtr = const __attribute__((address_space(4))) AT *;
 
-// One downward step of the scaled coefficient recurrence: e_j from
-// w = (e_{j+1}, e_{j+2}, e_{j+3}, e_{j+4}) with the row of k = j + 2.  The
-// newest value enters last, so the dependency chain is one multiply-add.
-// Rows above the start are zero and the start row has only its constant, so
-// every step is the same straight-line code.
-template <typename AT>
-__device__ __forceinline__ AT poly_coef_step(ConstPtr<AT> row, AT c, AT c2, AT w1, AT w2, AT w3, AT w4)
+// One downward step of the scaled coefficient recurrence, in the variables
+// f_j = e_j for even j and f_j = e_j / c for odd j: substituting them removes
+// every odd power of c, so with u = c^2
+//   even j:  f_j = u (alpha f_{j+1} + gamma f_{j+2} + delta f_{j+3}) + beta f_{j+2} + epsilon f_{j+4}
+//   odd j:   f_j = alpha f_{j+1} + (beta + gamma u) f_{j+2} + delta f_{j+3} + epsilon f_{j+4}
+// (the row of k = j + 2; w = (f_{j+1}, .., f_{j+4})), six multiply-adds with
+// at most one table value each.  Rows above the start shift (epsilon = 1), the
+// start row has epsilon = (-1)^N, and the window starts with a single 1 at the
+// position that the shifts carry to f_{2N+4}, so every step is the same
+// straight-line code.
+template <typename AT, bool ODD>
+__device__ __forceinline__ AT poly_coef_step(ConstPtr<AT> row, AT u, AT w1, AT w2, AT w3, AT w4)
 {
-    const AT rest = fmat(row[4], w4, fmat(fmat(row[2], c2, row[1]), w2, fmat(c * row[3], w3, row[5])));
-    return fmat(c * row[0], w1, rest);
+    if constexpr (ODD) {
+        AT r = row[1] * w2;
+        r = fmat(row[2], u * w2, r);
+        r = fmat(row[3], w3, r);
+        r = fmat(row[4], w4, r);
+        return fmat(row[0], w1, r);
+    } else {
+        AT t = row[0] * w1;
+        t = fmat(row[2], w2, t);
+        t = fmat(row[3], w3, t);
+        AT r = row[1] * w2;
+        r = fmat(row[4], w4, r);
+        return fmat(u, t, r);
+    }
 }
 
 // MULTI: more than one pass (the workspace carries the partial sums and the
@@ -232,24 +249,31 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                 if (actR && outlane) {
                     if (sR == 0) {
                         const AT c = (rc - mu) * irho;
-                        const AT c2 = c * c;
+                        const AT u = c * c;
                         rc = fetch(colok, rowc(iR + 1));
-                        // e_j for j from 2N down to k0 - 1; values above the
+                        // f_j for j from 2N down to k0 - 1; values above the
                         // register range only feed the recurrence
                         const long o = (long)iR * W + jx;
-                        const int jtop = k0 + 2 * KR;
-                        AT w1 = AT(0), w2 = AT(0), w3 = AT(0), w4 = AT(0);
+                        const int jtop = k0 + 2 * KR;   // even, as are k0 and 2N
+                        AT w1, w2, w3, w4;
                         if (top_pass) {
-#pragma unroll 2
-                            for (int j = n2; j > jtop; --j) {
-                                const AT e = poly_coef_step(rows + (long)kPolyRow * (j + 2), c, c2, w1, w2, w3, w4);
-                                w4 = w3;
-                                w3 = w2;
-                                w2 = w1;
-                                w1 = e;
+                            // the window above the first step j1 = max(2N, jtop):
+                            // a single 1 where the shifts carry it to f_{2N+4}
+                            const int j1 = max(n2, jtop);
+                            w1 = ((j1 + 1 - n2) & 3) == 0 ? AT(1) : AT(0);
+                            w2 = ((j1 + 2 - n2) & 3) == 0 ? AT(1) : AT(0);
+                            w3 = ((j1 + 3 - n2) & 3) == 0 ? AT(1) : AT(0);
+                            w4 = ((j1 + 4 - n2) & 3) == 0 ? AT(1) : AT(0);
+                            for (int j = n2; j > jtop; j -= 2) {
+                                const AT fe = poly_coef_step<AT, false>(rows + (long)kPolyRow * (j + 2), u, w1, w2, w3, w4);
+                                const AT fo = poly_coef_step<AT, true>(rows + (long)kPolyRow * (j + 1), u, fe, w1, w2, w3);
+                                w4 = w2;
+                                w3 = w1;
+                                w2 = fe;
+                                w1 = fo;
                             }
                         } else {
-                            // e_{jtop+1} .. e_{jtop+4}, from the pass above
+                            // f_{jtop+1} .. f_{jtop+4}, from the pass above
                             w1 = ws[2 * plane + o];
                             w2 = ws[3 * plane + o];
                             w3 = ws[4 * plane + o];
@@ -258,7 +282,9 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                         const ConstPtr<AT> rp = rows + (long)kPolyRow * (k0 + 1);   // row of j = k0 - 1
 #pragma unroll
                         for (int q = ND - 1; q >= 0; --q) {
-                            const AT e = poly_coef_step(rp + kPolyRow * q, c, c2, w1, w2, w3, w4);
+                            // j = k0 - 1 + q is odd exactly when q is even
+                            const AT e = (q & 1) ? poly_coef_step<AT, false>(rp + kPolyRow * q, u, w1, w2, w3, w4)
+                                                 : poly_coef_step<AT, true>(rp + kPolyRow * q, u, w1, w2, w3, w4);
                             dd[q] = e;
                             w4 = w3;
                             w3 = w2;
@@ -266,16 +292,17 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                             w1 = e;
                         }
                         if (!base) {
-                            // e_{k0+1} .. e_{k0+4} for the pass below
+                            // f_{k0+1} .. f_{k0+4} for the pass below
                             ws[2 * plane + o] = dd[2];
                             ws[3 * plane + o] = dd[3];
                             ws[4 * plane + o] = dd[4];
                             ws[5 * plane + o] = dd[5];
                         }
-                        // d_k = s_k e_k (s_k = 0 past the kept coefficients and for k = -1)
+                        // d_k = s_k e_k = s_k f_k (even k), s_k c f_k (odd k); s_k = 0
+                        // past the kept coefficients and for k = -1
                         const ConstPtr<AT> sp = sig + k0;
 #pragma unroll
-                        for (int q = 0; q < ND; ++q) dd[q] *= sp[q];
+                        for (int q = 0; q < ND; ++q) dd[q] *= (q & 1) ? sp[q] : sp[q] * c;
                         accQ = accP = AT(0);
                     }
 #pragma unroll
