@@ -204,12 +204,13 @@ struct PolForward {
         X[2] = aux[0] * C;
         X[3] = aux[0] * S;
     }
+    // accumulated as two chained multiply-adds per accumulator
     template <typename AT>
     __device__ static void recombine(AT v, AT vom, AT C, AT S, const AT *B, const AT *auxc, AT *acc)
     {
         const AT vc = v * C, vs = v * S;
-        acc[0] += vc * B[0] + vs * B[1];
-        acc[1] += vc * B[2] + vs * B[3];
+        acc[0] = fmat(vc, B[0], fmat(vs, B[1], acc[0]));
+        acc[1] = fmat(vc, B[2], fmat(vs, B[3], acc[1]));
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
@@ -264,12 +265,12 @@ struct PolTrain {
     __device__ static void recombine(AT v, AT vom, AT C, AT S, const AT *B, const AT *auxc, AT *acc)
     {
         const AT vc = v * C, vs = v * S;
-        acc[0] += vc * B[0] + vs * B[1];
-        acc[1] += vc * B[2] + vs * B[3];
+        acc[0] = fmat(vc, B[0], fmat(vs, B[1], acc[0]));
+        acc[1] = fmat(vc, B[2], fmat(vs, B[3], acc[1]));
         const AT wc = vom * C, ws = vom * S;
-        acc[2] -= wc * B[1] - ws * B[0];
-        acc[3] -= wc * B[3] - ws * B[2];
-        acc[4] -= wc * B[5] - ws * B[4];
+        acc[2] = fmat(ws, B[0], fmat(-wc, B[1], acc[2]));
+        acc[3] = fmat(ws, B[2], fmat(-wc, B[3], acc[3]));
+        acc[4] = fmat(ws, B[4], fmat(-wc, B[5], acc[4]));
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
