@@ -264,13 +264,29 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                             w2 = ((j1 + 2 - n2) & 3) == 0 ? AT(1) : AT(0);
                             w3 = ((j1 + 3 - n2) & 3) == 0 ? AT(1) : AT(0);
                             w4 = ((j1 + 4 - n2) & 3) == 0 ? AT(1) : AT(0);
-                            for (int j = n2; j > jtop; j -= 2) {
+                            // steps j, j - 1, ... down to jtop + 1, four at a time (the
+                            // window then rotates by renaming alone), after one pair of
+                            // steps when their count is not a multiple of four
+                            int j = n2;
+                            if (n2 > jtop && ((n2 - jtop) & 2)) {
                                 const AT fe = poly_coef_step<AT, false>(rows + (long)kPolyRow * (j + 2), u, w1, w2, w3, w4);
                                 const AT fo = poly_coef_step<AT, true>(rows + (long)kPolyRow * (j + 1), u, fe, w1, w2, w3);
                                 w4 = w2;
                                 w3 = w1;
                                 w2 = fe;
                                 w1 = fo;
+                                j -= 2;
+                            }
+                            for (; j > jtop; j -= 4) {
+                                const ConstPtr<AT> r0 = rows + (long)kPolyRow * (j - 1);   // row of j - 3
+                                const AT fa = poly_coef_step<AT, false>(r0 + 3 * kPolyRow, u, w1, w2, w3, w4);
+                                const AT fb = poly_coef_step<AT, true>(r0 + 2 * kPolyRow, u, fa, w1, w2, w3);
+                                const AT fc = poly_coef_step<AT, false>(r0 + kPolyRow, u, fb, fa, w1, w2);
+                                const AT fd = poly_coef_step<AT, true>(r0, u, fc, fb, fa, w1);
+                                w4 = fa;
+                                w3 = fb;
+                                w2 = fc;
+                                w1 = fd;
                             }
                         } else {
                             // f_{jtop+1} .. f_{jtop+4}, from the pass above
