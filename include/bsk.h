@@ -97,7 +97,8 @@ typedef struct {
     int order_chunk;      /* orders per pass, one of the two pass sizes of the kernel that runs:
                              FP32 forward 256: 16|8, 512: 8|4, 1024: 4|2 (lanes: full|half);
                              adjoint 256: 16|8, 512: 8|4, 1024: 2|1; spatial kernel 4|2
-                             (one frequency) or 2|1; ignored by FP64 and the training
+                             (one frequency) or 2|1; polynomial range kernel (channel pairs)
+                             256 and 512: 16|8, 1024: 8|4; ignored by FP64 and the training
                              forward; 0 = automatic (the cheaper for the order count) */
     /* Spatial kernel (Algorithms 1 and 2 with M > 1; Section 3, separable
      * kernels): 0 = the box; Ns in 1..6 = the separable raised cosine

@@ -295,3 +295,11 @@ def test_poly_kernel_errors(lib):
     d = (_lib.ImageDesc * 1)()
     d[0].img, d[0].out, d[0].H, d[0].W, d[0].radius, d[0].sigma_r, d[0].N = big, big2, 8, 8, 2, 30.0, -1
     assert lib.bilateral_shiftable_batched(d, 1, 255.0, ctypes.byref(o), None) == _lib.BSK_EUNSUPPORTED
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without libbsk.so the binding raises; there is no fallback implementation."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libbsk.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        _lib.load()
