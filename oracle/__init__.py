@@ -9,7 +9,8 @@ box spatial window and the rescaled raised-cosine range kernel of eq. (6),
 cos^N(t / (sigma_r sqrt N)); the ``*_sp`` entry points add the separable
 raised-cosine spatial kernel of Algorithms 1 and 2 with M > 1, and the
 ``*_poly`` entry points use the polynomial range kernel p_N of Section 3 in the
-scaling of eq. (5), (1 - t^2 / (2 N sigma_r^2))^N.  See its header
+scaling of eq. (5), (1 - t^2 / (2 N sigma_r^2))^N; the ``nlm2`` entry points
+compute the two-pixel-patch non-local means of Section 5.  See its header
 for the definitions.  This module only marshals NumPy arrays.
 """
 from __future__ import annotations
@@ -95,6 +96,14 @@ def _load():
     lib.oracle_bilateral_poly_at.restype = None
     lib.oracle_bilateral_poly_at.argtypes = [_fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                              ctypes.c_int, _llp, ctypes.c_longlong, _dp]
+    _ci = ctypes.c_int
+    _cd = ctypes.c_double
+    lib.oracle_nlm2_f64.restype = None
+    lib.oracle_nlm2_f64.argtypes = [_dp, _ci, _ci, _ci, _cd, _ci, _cd, _ci, _ci, _ci, _dp, _dp, _dp]
+    lib.oracle_nlm2.restype = None
+    lib.oracle_nlm2.argtypes = [_fp, _ci, _ci, _ci, _cd, _ci, _cd, _ci, _ci, _ci, _dp, _dp, _dp]
+    lib.oracle_nlm2_at.restype = None
+    lib.oracle_nlm2_at.argtypes = [_fp, _ci, _ci, _ci, _cd, _ci, _cd, _ci, _ci, _ci, _llp, ctypes.c_longlong, _dp]
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -248,4 +257,35 @@ def bilateral_poly_at(f, idx, radius: int, sigma_r: float, N: int):
     out = np.empty(idx.size, np.float64)
     _load().oracle_bilateral_poly_at(_ptr(f, _fp), H, W, int(radius), float(sigma_r), int(N),
                                      _ptr(idx, _llp), idx.size, _ptr(out, _dp))
+    return out
+
+
+def nlm2(f, radius: int, sigma_1: float, N1: int, sigma_2: float, N2: int, offset, return_pq: bool = False):
+    """Two-pixel-patch non-local means (Section 5, p = 2): patches {y, y + offset}, range kernel
+    cos^N1(t1 / (sigma_1 sqrt N1)) cos^N2(t2 / (sigma_2 sqrt N2)); offset = (uy, ux)."""
+    f = np.ascontiguousarray(f)
+    H, W = f.shape
+    uy, ux = (int(v) for v in offset)
+    out = np.empty((H, W), np.float64)
+    P = np.empty((H, W), np.float64) if return_pq else None
+    Q = np.empty((H, W), np.float64) if return_pq else None
+    if f.dtype == np.float64:
+        _load().oracle_nlm2_f64(_ptr(f, _dp), H, W, int(radius), float(sigma_1), int(N1), float(sigma_2), int(N2),
+                                uy, ux, _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    else:
+        f32 = np.ascontiguousarray(f, dtype=np.float32)
+        _load().oracle_nlm2(_ptr(f32, _fp), H, W, int(radius), float(sigma_1), int(N1), float(sigma_2), int(N2),
+                            uy, ux, _ptr(out, _dp), _ptr(P, _dp), _ptr(Q, _dp))
+    return (out, P, Q) if return_pq else out
+
+
+def nlm2_at(f, idx, radius: int, sigma_1: float, N1: int, sigma_2: float, N2: int, offset):
+    """The two-pixel-patch filter at the flat (row-major) pixel indices ``idx`` only."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    H, W = f.shape
+    uy, ux = (int(v) for v in offset)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size, np.float64)
+    _load().oracle_nlm2_at(_ptr(f, _fp), H, W, int(radius), float(sigma_1), int(N1), float(sigma_2), int(N2),
+                           uy, ux, _ptr(idx, _llp), idx.size, _ptr(out, _dp))
     return out

@@ -39,6 +39,12 @@
  * The *_sp functions add the separable raised-cosine spatial kernel of
  * Algorithms 1 and 2 with M > 1 (defined with oracle_spatial_weight below).
  *
+ * The *_nlm2 functions compute the two-pixel-patch form of the non-local
+ * means filter of the Discussion (Section 5): the range kernel compares the
+ * patches {y, y + u} and {x, x + u} through the separable product of two
+ * raised cosines, one per patch pixel (the shiftable approximation of the
+ * anisotropic Gaussian phi(t_1, .., t_p) with p = 2).
+ *
  * The *_poly functions use instead the polynomial range kernel p_N of
  * Section 3 in the scaling of the Gaussian-approximation theorem, eq. (5):
  * p_N(t / sqrt N) with the bound T of p_N set to sqrt(2) sigma_r, i.e.
@@ -575,6 +581,88 @@ void oracle_bilateral_poly_at(const float *f, int H, int W, int radius, double s
         }
         out[s] = p / q;
     }
+}
+
+/* ---- two-pixel-patch non-local means (Section 5, p = 2) ----
+ *
+ * For pixel x and window pixel y in B(x) (the truncated (2r+1)^2 square):
+ *     t_1 = f(x) - f(y),   t_2 = fe(x + u) - fe(y + u),
+ *     phi(t_1, t_2) = [cos(t_1 / (sigma_1 sqrt N_1))]^N_1 [cos(t_2 / (sigma_2 sqrt N_2))]^N_2,
+ *     out(x) = sum_y phi f(y) / sum_y phi,
+ * where u = (uy, ux) is the second patch pixel's offset and fe extends f
+ * beyond the image by its nearest border pixel (the paper does not discuss
+ * borders; this reading keeps every patch complete).  Each factor is the
+ * raised cosine of eq. (6) with its own scale: the Gaussian
+ * exp(-h^-2 (g_1 t_1^2 + g_2 t_2^2)) of the Discussion has sigma_k =
+ * h / sqrt(2 g_k).  N_k = 0 makes factor k equal to 1. */
+static inline double ext(const double *f, long H, long W, long i, long j)
+{
+    i = i < 0 ? 0 : (i >= H ? H - 1 : i);
+    j = j < 0 ? 0 : (j >= W ? W - 1 : j);
+    return f[i * W + j];
+}
+
+static void window_pq_nlm2(const double *f, long H, long W, long r, double s1, int N1, double s2, int N2,
+                           long uy, long ux, long i, long j, double *P, double *Q)
+{
+    double fx = f[i * W + j];
+    double gx = ext(f, H, W, i + uy, j + ux);
+    double p = 0.0, q = 0.0;
+    long y0 = lmax(0, i - r), y1 = lmin(H - 1, i + r);
+    long x0 = lmax(0, j - r), x1 = lmin(W - 1, j + r);
+    for (long y = y0; y <= y1; ++y) {
+        for (long x = x0; x <= x1; ++x) {
+            double fy = f[y * W + x];
+            double gy = ext(f, H, W, y + uy, x + ux);
+            double kv = oracle_kernel(fy - fx, s1, N1) * oracle_kernel(gy - gx, s2, N2);
+            p += kv * fy;
+            q += kv;
+        }
+    }
+    *P = p;
+    *Q = q;
+}
+
+/* Full image, double input; out, P, Q may be NULL independently. */
+void oracle_nlm2_f64(const double *f, int H, int W, int radius, double sigma_1, int N1, double sigma_2, int N2,
+                     int uy, int ux, double *out, double *P, double *Q)
+{
+    long r = clamp_radius(radius, H, W);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < H; ++i) {
+        for (long j = 0; j < W; ++j) {
+            double p, q;
+            window_pq_nlm2(f, H, W, r, sigma_1, N1, sigma_2, N2, uy, ux, i, j, &p, &q);
+            if (out) out[i * W + j] = p / q;
+            if (P) P[i * W + j] = p;
+            if (Q) Q[i * W + j] = q;
+        }
+    }
+}
+
+/* The same with float input (widened exactly). */
+void oracle_nlm2(const float *f, int H, int W, int radius, double sigma_1, int N1, double sigma_2, int N2,
+                 int uy, int ux, double *out, double *P, double *Q)
+{
+    double *d = widen(f, (long)H * W);
+    oracle_nlm2_f64(d, H, W, radius, sigma_1, N1, sigma_2, N2, uy, ux, out, P, Q);
+    free(d);
+}
+
+/* Selected pixels only (flat row-major indices), float input. */
+void oracle_nlm2_at(const float *f, int H, int W, int radius, double sigma_1, int N1, double sigma_2, int N2,
+                    int uy, int ux, const long long *idx, long long n, double *out)
+{
+    double *d = widen(f, (long)H * W);
+    long r = clamp_radius(radius, H, W);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long long s = 0; s < n; ++s) {
+        long i = (long)(idx[s] / W), j = (long)(idx[s] % W);
+        double p, q;
+        window_pq_nlm2(d, H, W, r, sigma_1, N1, sigma_2, N2, uy, ux, i, j, &p, &q);
+        out[s] = p / q;
+    }
+    free(d);
 }
 
 int oracle_num_threads(void)

@@ -650,3 +650,116 @@ def test_poly_sampled_matches_full(oracle):
     full = oracle.bilateral_poly(f, 5, 30.0, 37)
     idx = np.array([0, 49, 50 * 39, 40 * 50 - 1, 777, 1234, 1500])
     assert np.array_equal(oracle.bilateral_poly_at(f, idx, 5, 30.0, 37), full.ravel()[idx])
+
+
+# ------------------------------------ two-pixel-patch non-local means (Section 5) ----
+@pytest.mark.parametrize("offset", [(0, 1), (1, 0), (-2, 3)])
+def test_nlm2_second_order_zero_is_bilateral(oracle, offset):
+    """N2 = 0 drops the second patch pixel: the bilateral filter of eq. (3)."""
+    f = wl.random_image(14, 17, 2)
+    a = oracle.nlm2(f, 3, 30.0, 30, 40.0, 0, offset)
+    assert np.max(np.abs(a - oracle.bilateral(f, 3, 30.0, 30))) < 1e-12
+
+
+def test_nlm2_zero_offset_closed_form(oracle):
+    """u = 0 compares each pixel twice: cos^N(t / (s sqrt N))^2 = cos^2N(t / ((s / sqrt 2) sqrt 2N)),
+    the bilateral filter of order 2N at sigma_r / sqrt 2."""
+    f = wl.random_image(12, 15, 3)
+    a = oracle.nlm2(f, 2, 50.0, 9, 50.0, 9, (0, 0))
+    b = oracle.bilateral(f, 2, 50.0 / math.sqrt(2.0), 18)
+    assert np.max(np.abs(a - b)) < 1e-10
+
+
+def _nlm2_brute(f, r, s1, N1, s2, N2, off):
+    """Eq. (NL) with p = 2 in pure Python, each factor as its exact binomial sum of cosines."""
+    H, W = f.shape
+    uy, ux = off
+    fe = lambda i, j: float(f[min(max(i, 0), H - 1), min(max(j, 0), W - 1)])
+    out = np.empty((H, W))
+    for i in range(H):
+        for j in range(W):
+            fx, gx = float(f[i, j]), fe(i + uy, j + ux)
+            ps, qs = [], []
+            for y in range(max(0, i - r), min(H - 1, i + r) + 1):
+                for x in range(max(0, j - r), min(W - 1, j + r) + 1):
+                    k = _binom_kernel(float(f[y, x]) - fx, s1, N1) * _binom_kernel(fe(y + uy, x + ux) - gx, s2, N2)
+                    ps.append(k * float(f[y, x]))
+                    qs.append(k)
+            out[i, j] = math.fsum(ps) / math.fsum(qs)
+    return out
+
+
+@pytest.mark.parametrize("r,N1,N2,off,shape", [(1, 30, 14, (0, 1), (7, 9)), (2, 30, 20, (1, 0), (9, 8)),
+                                               (3, 31, 15, (-1, 2), (8, 11))])
+def test_nlm2_brute_force_small(oracle, r, N1, N2, off, shape):
+    """Orders at or above N_0 of each factor (30 at sigma 30, 14 at sigma 45), so the kernel
+    is non-negative and the ratio well conditioned."""
+    f = wl.random_image(*shape, seed=21 + r)
+    ref = _nlm2_brute(f, r, 30.0, N1, 45.0, N2, off)
+    assert np.max(np.abs(oracle.nlm2(f, r, 30.0, N1, 45.0, N2, off) - ref)) <= 1e-11 * T
+
+
+def _nlm2_shiftable(f, r, s1, N1, s2, N2, off):
+    """Algorithm 2 with the two-pixel patch in NumPy FP64: the product kernel expands into
+    cos(w1 t1 + w2 t2) terms (all w1, folded w2), each giving the channels cos(psi), sin(psi),
+    f cos(psi), f sin(psi) of the patch phase psi(z) = w1 f(z) + w2 fe(z + u), box-summed through
+    integral images and recombined by the shift identity."""
+    f = f.astype(np.float64)
+    H, W = f.shape
+    uy, ux = off
+    ii = np.clip(np.arange(H) + uy, 0, H - 1)
+    jj = np.clip(np.arange(W) + ux, 0, W - 1)
+    g = f[ii][:, jj]
+
+    def box(X):
+        S = np.zeros((H + 1, W + 1))
+        S[1:, 1:] = np.cumsum(np.cumsum(X, 0), 1)
+        i = np.arange(H)[:, None]
+        j = np.arange(W)[None, :]
+        y0, y1 = np.maximum(i - r, 0), np.minimum(i + r, H - 1) + 1
+        x0, x1 = np.maximum(j - r, 0), np.minimum(j + r, W - 1) + 1
+        return S[y1, x1] - S[y0, x1] - S[y1, x0] + S[y0, x0]
+
+    terms1 = [(math.comb(N1, n) / 2 ** N1, (2 * n - N1) / (s1 * math.sqrt(N1)) if N1 else 0.0)
+              for n in range(N1 + 1)]
+    terms2 = []
+    for n in range((N2 + 1) // 2):
+        terms2.append((2.0 * math.comb(N2, n) / 2 ** N2, (N2 - 2 * n) / (s2 * math.sqrt(N2))))
+    if N2 % 2 == 0:
+        terms2.append((math.comb(N2, N2 // 2) / 2 ** N2, 0.0))
+    P = np.zeros((H, W))
+    Q = np.zeros((H, W))
+    for w1, om1 in terms1:
+        for w2, om2 in terms2:
+            psi = om1 * f + om2 * g
+            C, S_ = np.cos(psi), np.sin(psi)
+            P += w1 * w2 * (C * box(f * C) + S_ * box(f * S_))
+            Q += w1 * w2 * (C * box(C) + S_ * box(S_))
+    return P / Q
+
+
+@pytest.mark.parametrize("r,N1,N2,off", [(2, 8, 8, (0, 1)), (3, 10, 6, (2, -1)), (4, 5, 9, (1, 1))])
+def test_nlm2_moving_sum_evaluation(oracle, r, N1, N2, off):
+    f = wl.smooth_image(30, 37, seed=4)
+    ref = _nlm2_shiftable(f, r, 60.0, N1, 70.0, N2, off)
+    assert np.max(np.abs(oracle.nlm2(f, r, 60.0, N1, 70.0, N2, off) - ref)) <= 1e-10 * T
+
+
+def test_nlm2_invariants(oracle):
+    rng = np.random.default_rng(26)
+    f = rng.uniform(0, 200, (13, 16))
+    base = oracle.nlm2(f, 3, 30.0, 30, 40.0, 20, (1, 2))
+    assert np.max(np.abs(oracle.nlm2(np.full((9, 8), 77.0), 2, 30.0, 30, 40.0, 20, (1, 2)) - 77.0)) < 1e-12
+    assert np.max(np.abs(oracle.nlm2(f + 40.0, 3, 30.0, 30, 40.0, 20, (1, 2)) - (base + 40.0))) < 1e-10
+    assert np.max(np.abs(oracle.nlm2(2.0 * f, 3, 60.0, 30, 80.0, 20, (1, 2)) - 2.0 * base)) < 1e-11
+    # transposing the image transposes the offset; flipping the rows negates its row part
+    assert np.max(np.abs(oracle.nlm2(np.ascontiguousarray(f.T), 3, 30.0, 30, 40.0, 20, (2, 1)) - base.T)) < 1e-11
+    assert np.max(np.abs(oracle.nlm2(np.ascontiguousarray(f[::-1]), 3, 30.0, 30, 40.0, 20, (-1, 2))
+                         - base[::-1])) < 1e-11
+
+
+def test_nlm2_sampled_matches_full(oracle):
+    f = wl.rect_image(40, 50, seed=7)
+    full = oracle.nlm2(f, 5, 30.0, 30, 40.0, 20, (0, 1))
+    idx = np.array([0, 49, 50 * 39, 40 * 50 - 1, 777, 1234])
+    assert np.array_equal(oracle.nlm2_at(f, idx, 5, 30.0, 30, 40.0, 20, (0, 1)), full.ravel()[idx])
