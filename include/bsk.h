@@ -153,6 +153,29 @@ int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigm
                            void *out, const bsk_options *opt, void *stream);
 
 /*
+ * Two-pixel-patch non-local means (Section 5, the Discussion, with p = 2
+ * patch pixels u_1 = 0 and u_2 = (uy, ux)): the bilateral filter of eq. (3)
+ * with the range kernel comparing the patches {x, x + u_2} and {y, y + u_2},
+ *     phi = cos^N1(t_1 / (sigma_1 sqrt N1)) cos^N2(t_2 / (sigma_2 sqrt N2)),
+ *     t_1 = f(x) - f(y),   t_2 = f(x + u_2) - f(y + u_2),
+ * the separable shiftable approximation of the Discussion's anisotropic
+ * Gaussian exp(-h^-2 (g_1 t_1^2 + g_2 t_2^2)) (sigma_k = h / sqrt(2 g_k)).
+ * Patch pixels beyond the image read its nearest border pixel; the window
+ * B(x) is the truncated (2r+1)^2 square of the box kernel.  The expansion has
+ * (N1 + 1) times the folded orders of N2 terms (the order grows as n^p, which
+ * is why larger patches are not offered).
+ *   img, out:  device FP32, as for bilateral_shiftable_ex (must not overlap)
+ *   N1, N2:    orders, or < 0 for N_0(sigma_k, T); at most 1000 each
+ *   opt:       NULL or options with order_mode 0, FP32, no compensation, the
+ *              box spatial kernel and the raised cosine; weight_eps > 0 drops
+ *              terms of either factor whose binomial weight is below it;
+ *              pitches, block, strip_h and order_chunk as for the forward
+ * Asynchronous on `stream`.  BSK_ERANGE when more than 65536 terms remain.
+ */
+int bilateral_shiftable_nlm2(const float *img, int H, int W, int radius, float sigma_1, float sigma_2, int N1,
+                             int N2, int uy, int ux, float T, float *out, const bsk_options *opt, void *stream);
+
+/*
  * Training forward (FP32): the filter output plus what the adjoint needs.
  *   out:   device H*W floats: u = P/Q
  *   saved: device 3*H*W floats, planar: Q (the normaliser eta of eq. (3)),

@@ -9,7 +9,7 @@ C ABI (include/bsk.h).  The torch-facing calls live in `filter`; importing this
 package does not touch the GPU.
 """
 from .filter import (BilateralFunction, ShiftableBilateral, autotune, bilateral, bilateral_backward,  # noqa: F401
-                     bilateral_batched, bilateral_train, order_for, plan_info, poly_order_for, poly_plan_info,
-                     release, spatial_filter, spatial_sigma_for)
+                     bilateral_batched, bilateral_train, nlm2, order_for, plan_info, poly_order_for,
+                     poly_plan_info, release, spatial_filter, spatial_sigma_for)
 
 __version__ = "0.1.0"

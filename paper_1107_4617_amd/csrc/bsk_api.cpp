@@ -163,7 +163,9 @@ static int kernel_occupancy(const Resolved &r, int kind)
     bsk::StripArgs a;
     std::memset(&a, 0, sizeof(a));
     int occ = 1;
-    if (r.range_kernel == BSK_RANGE_POLY) {
+    if (kind == kPatch2) {
+        (void)bsk::launch_patch2_f32(a, r.block, r.kc, nullptr, &occ);
+    } else if (r.range_kernel == BSK_RANGE_POLY) {
         bsk::PolyArgs pa;
         std::memset(&pa, 0, sizeof(pa));
         if (r.prec == BSK_FP64) (void)bsk::launch_poly_f64(pa, r.block, nullptr, &occ);
@@ -213,6 +215,12 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     const bool poly = o.range_kernel == BSK_RANGE_POLY;
     r->poly.reset();
     r->poly_pairs = 0;
+    if (kind == kPatch2) {
+        if (poly || o.spatial_N != 0)
+            return fail(BSK_EUNSUPPORTED, "the two-pixel patch uses the raised cosine and the box window");
+        if (r->prec != BSK_FP32 || r->kahan)
+            return fail(BSK_EUNSUPPORTED, "the two-pixel patch runs in plain FP32");
+    }
     if (poly) {
         if (kind != kForward) return fail(BSK_EUNSUPPORTED, "the polynomial range kernel has the forward filter only");
         if (o.spatial_N != 0) return fail(BSK_EUNSUPPORTED, "the polynomial range kernel uses the box spatial kernel");
@@ -331,6 +339,11 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         } else {
             kc = pick_chunk(r->plan.K, full, small);
         }
+    } else if (kind == kPatch2) {
+        // the caller picks between the two pass sizes; residency is the same
+        if (kc == 0) kc = bsk::chunk_forward_f32(block);
+        if (!bsk::valid_chunk_forward_f32(block, kc))
+            return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     } else if (kind == kTrain) {
         kc = bsk::chunk_train_f32(block);
     } else if (kind == kBackward) {
@@ -498,6 +511,149 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
     return BSK_OK;
 }
 
+// Small per-call tables (the two-pixel patch's weights), uploaded to a
+// workspace slot of the stream when their contents or the buffer change.
+struct TabUpload {
+    std::vector<unsigned char> host;
+    void *ptr = nullptr;
+};
+std::mutex g_tab_mu;
+std::map<std::tuple<int, void *, int>, TabUpload> g_tab_up;
+
+int upload_table(void *stream, int slot, const std::vector<unsigned char> &bytes, void **out)
+{
+    void *dst = nullptr;
+    int st = get_ws(stream, slot, bytes.size(), &dst);
+    if (st) return st;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    TabUpload &u = g_tab_up[std::make_tuple(dev, stream, slot)];
+    if (u.ptr != dst || u.host != bytes) {
+        if (!u.host.empty()) {
+            // an earlier upload from the host copy may still be pending on the stream
+            e = hipStreamSynchronize((hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        }
+        u.host = bytes;
+        e = hipMemcpyAsync(dst, u.host.data(), u.host.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "table upload");
+        u.ptr = dst;
+    }
+    *out = dst;
+    return BSK_OK;
+}
+
+int nlm2_impl(const float *img, int H, int W, int radius, float sigma_1, float sigma_2, int N1, int N2, int uy,
+              int ux, float T, float *out, const bsk_options *opt, void *stream)
+{
+    if (!img || !out) return fail(BSK_EINVAL, "null image pointer");
+    if (!finite_pos(sigma_2)) return fail(BSK_EINVAL, "sigma_2 must be finite and > 0");
+    if (!finite_pos(sigma_1) || !finite_pos(T)) return fail(BSK_EINVAL, "sigma_1 and T must be finite and > 0");
+    bsk_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    if (o.order_mode != 0) return fail(BSK_EINVAL, "the orders of the two-pixel patch are the N1 and N2 arguments");
+    auto order = [&](int N, float sigma, int *res) -> int {
+        if (N >= 0) {
+            *res = N;
+        } else {
+            const double x = 2.0 * (double)T / (M_PI * (double)sigma);
+            if (!(x * x < 1e6)) return fail(BSK_ERANGE, "automatic order too large");
+            *res = bsk::order_for(sigma, T);
+        }
+        if (*res > 1000) return fail(BSK_ERANGE, "order %d exceeds 1000", *res);
+        return BSK_OK;
+    };
+    int n1 = 0, n2 = 0;
+    int st = order(N1, sigma_1, &n1);
+    if (st) return st;
+    st = order(N2, sigma_2, &n2);
+    if (st) return st;
+    // launch shape: the forward's rules at the first pixel's order
+    bsk_options ro = o;
+    ro.order_mode = 1;
+    ro.N = n1;
+    Resolved r;
+    st = resolve(H, W, radius, sigma_1, T, &ro, &r, kPatch2);
+    if (st) return st;
+    if (overlap(img, ((size_t)(H - 1) * r.pitch_in + W) * 4, out, ((size_t)(H - 1) * r.pitch_out + W) * 4))
+        return fail(BSK_EINVAL, "img and out overlap");
+
+    // First pixel: the unfolded terms n of cos^N1 (frequency (2n - N1) / (sigma_1 sqrt N1),
+    // weight 2^-N1 C(N1, n)) whose weight is at least eps, a contiguous range since
+    // the weights are unimodal; second pixel: the folded plan of cos^N2.
+    std::vector<double> w1;
+    int nlo = 0;
+    {
+        double lw = -(double)n1 * std::log(2.0);   // log weight of n = 0
+        for (int n = 0; n <= n1; ++n) {
+            const double w = std::exp(lw);
+            if (o.weight_eps <= 0.0 || w >= o.weight_eps) {
+                if (w1.empty()) nlo = n;
+                w1.push_back(w);
+            }
+            lw += std::log((double)(n1 - n)) - std::log((double)(n + 1));
+        }
+    }
+    bsk::Plan p2;
+    if (bsk::make_plan(n2, sigma_2, o.weight_eps, &p2) != 0)
+        return fail(BSK_ERANGE, "order N2=%d leaves more than %d folded orders", n2, bsk::kMaxOrders);
+    const int K1 = (int)w1.size(), K2 = p2.K;
+    int kc = r.kc;
+    if (o.order_chunk == 0) {
+        // pass size: a pass stays within one first-pixel term
+        const int full = bsk::chunk_forward_f32(r.block);
+        auto cost = [&](int c) { return (double)K1 * ((K2 + c - 1) / c) * (c + 2.5 + 0.1 * c); };
+        kc = cost(full / 2) < cost(full) ? full / 2 : full;
+    }
+    const int G2 = (K2 + kc - 1) / kc * kc;
+    const long long K = (long long)K1 * G2;
+    if (K > 65536) return fail(BSK_ERANGE, "%lld patch orders (raise weight_eps or the sigmas)", K);
+    std::vector<unsigned char> tab((size_t)K * sizeof(float), 0);
+    float *vf = (float *)tab.data();
+    for (int g = 0; g < K1; ++g)
+        for (int m = 0; m < K2; ++m) vf[(size_t)g * G2 + m] = (float)(w1[g] * p2.v[m]);
+    void *dtab = nullptr;
+    st = upload_table(stream, 7, tab, &dtab);
+    if (st) return st;
+
+    bsk::StripArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.io.img = img;
+    a.io.out = out;
+    a.io.H = H;
+    a.io.W = W;
+    a.io.pitch_in = r.pitch_in;
+    a.io.pitch_out = r.pitch_out;
+    a.io.uy = uy;
+    a.io.ux = ux;
+    a.rh = r.rh;
+    a.rv = r.rv;
+    a.S = r.S;
+    a.K = (int)K;
+    a.start_mode = 2;
+    a.omega_base = p2.omega_base;
+    a.delta = p2.delta;
+    const int Wt = r.block - 2 * r.rh;
+    a.strips = (W + Wt - 1) / Wt;
+    a.p2_group = G2;
+    const double s1 = n1 > 0 ? 1.0 / ((double)sigma_1 * std::sqrt((double)n1)) : 0.0;
+    a.p2_omega1_base = (double)(2 * nlo - n1) * s1;
+    a.p2_delta1 = 2.0 * s1;
+    a.vf_dev = (const float *)dtab;
+    if (K > kc) {
+        void *ws = nullptr;
+        st = get_ws(stream, 0, (size_t)bsk::acc_count_forward() * H * W * 4, &ws);
+        if (st) return st;
+        a.ws = ws;
+    }
+    hipError_t e = bsk::launch_patch2_f32(a, r.block, kc, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "two-pixel-patch launch");
+    return BSK_OK;
+}
+
 int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
                  const bsk_options *opt, void *stream)
 {
@@ -580,6 +736,12 @@ int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigm
                            const bsk_options *opt, void *stream)
 {
     return forward_impl(img, H, W, radius, sigma_r, T, out, opt, stream);
+}
+
+int bilateral_shiftable_nlm2(const float *img, int H, int W, int radius, float sigma_1, float sigma_2, int N1,
+                             int N2, int uy, int ux, float T, float *out, const bsk_options *opt, void *stream)
+{
+    return nlm2_impl(img, H, W, radius, sigma_1, sigma_2, N1, N2, uy, ux, T, out, opt, stream);
 }
 
 int bilateral_shiftable_train(const float *img, int H, int W, int radius, float sigma_r, float T,
@@ -718,7 +880,7 @@ int bsk_release(void)
             int cur = 0;
             (void)hipGetDevice(&cur);
             (void)hipSetDevice(kv.first.dev);
-            hipFree(kv.second.ptr);
+            (void)hipFree(kv.second.ptr);
             (void)hipSetDevice(cur);
         }
     }
@@ -726,6 +888,10 @@ int bsk_release(void)
     {
         std::lock_guard<std::mutex> lp(g_poly_mu);
         g_poly_up.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lt(g_tab_mu);
+        g_tab_up.clear();
     }
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     return BSK_OK;

@@ -220,6 +220,76 @@ struct PolForward {
     }
 };
 
+// Two-pixel-patch non-local means (Section 5 with p = 2): the range kernel
+// compares the patches {z, z + u} through cos^N1(w t_1) cos^N2(w' t_2), whose
+// expansion holds terms cos(omega_1 t_1 + omega_2 t_2).  A term's channels are
+// those of the forward policy with the patch phase
+// psi(z) = omega_1 g(z) + omega_2 g(z + u) in place of omega g(z); the second
+// patch pixel lies beyond the image only through the clamped read (the image
+// extended by its nearest border pixel).
+struct PolPatch2 {
+    static constexpr int NCH = 4, NACC = 2, NAUX = 2, NRAW = 2, NPAIR = 2;
+    template <typename AT>
+    __device__ static void kappa(const AT *aux, AT *k)
+    {
+        k[0] = AT(1);
+        k[1] = aux[0];
+    }
+    template <typename AT>
+    __device__ static AT ref(const IO &a, int i, int j)
+    {
+        return (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
+    }
+    template <typename AT>
+    __device__ static void fetch(const IO &a, bool valid, int i, int j, AT *raw)
+    {
+        const int i2 = min(max(i + a.uy, 0), a.H - 1);
+        const int j2 = min(max(j + a.ux, 0), a.W - 1);
+        const AT x = (AT)ld<float>(a.img, (long)i * a.pitch_in + j);
+        const AT x2 = (AT)ld<float>(a.img, (long)i2 * a.pitch_in + j2);
+        raw[0] = valid ? x : AT(0);
+        raw[1] = valid ? x2 : AT(0);
+    }
+    template <typename AT>
+    __device__ static void make(const AT *raw, AT ref, AT *aux)
+    {
+        aux[0] = raw[0] - ref;
+        aux[1] = raw[1] - ref;
+    }
+    template <typename AT>
+    __device__ static void recombine(AT v, AT vom, AT C, AT S, const AT *B, const AT *auxc, AT *acc)
+    {
+        PolForward<float>::recombine<AT>(v, vom, C, S, B, auxc, acc);
+    }
+    template <typename AT>
+    __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
+                                    double *red)
+    {
+        ((float *)a.out)[(long)i * a.pitch_out + j] = (float)(ref + acc[1] / acc[0]);
+    }
+};
+template <class P>
+struct IsPatch2 {
+    static constexpr bool value = false;
+};
+template <>
+struct IsPatch2<PolPatch2> {
+    static constexpr bool value = true;
+};
+
+// Start of an order chain: the angle omega g of one value, or for the
+// two-pixel patch the phase omega_1 g_1 + omega_2 g_2 (om1 = omega_1) with the
+// step delta g_2 of the second value.
+template <class POL, typename AT>
+__device__ __forceinline__ void chain_start(Chain<AT> &ch, bool valid, const AT *aux, AT om0, AT dlt, int mode,
+                                            AT om1)
+{
+    if constexpr (IsPatch2<POL>::value)
+        ch.start(valid, AT(1), fmat(om1, aux[0], om0 * aux[1]), dlt * aux[1], 2);
+    else
+        ch.start(valid, aux[0], om0, dlt, mode);
+}
+
 // Training forward: channels (C, S, gC, gS, g^2 C, g^2 S); accumulators
 // (Q, P, A0, A1, A2) with A_p(z) = sum_{y in B(z)} phi'(g_y - g_z) g_y^p
 //   = -sum_m v_m omega_m [C_m(z) Box[g^p S_m] - S_m(z) Box[g^p C_m]],
@@ -366,7 +436,18 @@ struct Geom {
     float sp_u[kMaxSpatialFreq];
     const float *sp_row;
     const float *sp_col;
+    // two-pixel patch: orders per first-pixel frequency, those frequencies,
+    // and the weights (device memory)
+    int p2_group;
+    double p2_omega1_base, p2_delta1;
+    const float *p2_vf;
 };
+
+// Read-only tables read at workgroup-uniform addresses: through the constant
+// address space the compiler fetches them with scalar loads into SGPRs
+// instead of one vector load per lane.
+template <typename AT>
+using ConstPtr = const __attribute__((address_space(4))) AT *;
 
 template <typename AT>
 __device__ __forceinline__ AT weight(const Geom &gm, int m);
@@ -568,9 +649,17 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     for (int m0 = 0; m0 < gm.K; m0 += KR) {
         const bool first = (m0 == 0);
         const bool last = (m0 + KR >= gm.K);
-        const AT om0 = (AT)(gm.omega_base + (double)m0 * gm.delta);
+        AT om0 = (AT)(gm.omega_base + (double)m0 * gm.delta);
         const AT dlt = (AT)gm.delta;
         const int smode = first ? gm.start_mode : 2;
+        AT om1 = AT(0);
+        if constexpr (IsPatch2<POL>::value) {
+            // a pass lies within one group: its first-pixel frequency, and the
+            // second pixel's frequency of its first order
+            const int n1 = m0 / gm.p2_group;
+            om1 = (AT)(gm.p2_omega1_base + (double)n1 * gm.p2_delta1);
+            om0 = (AT)(gm.omega_base + (double)(m0 - n1 * gm.p2_group) * gm.delta);
+        }
 
         AT V[KR][NCH];
         AT Cmp[KAHAN ? KR : 1][NCH];
@@ -608,7 +697,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     }
                 }
                 Chain<AT> ch;
-                ch.start(colok, aux[0], om0, dlt, smode);
+                chain_start<POL>(ch, colok, aux, om0, dlt, smode, om1);
 #pragma unroll
                 for (int m = 0; m < KR; ++m) {
                     const AT C = quant<QUANT>(ch.c), S = quant<QUANT>(ch.s);
@@ -688,7 +777,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     if (sR == 0) {
                         POL::template make<AT>(rc, ref, auxc);
                         POL::template fetch<AT>(a, colok, rowc(iR + 1), jxc, rc);
-                        cc.start(colok, auxc[0], om0, dlt, smode);
+                        chain_start<POL>(cc, colok, auxc, om0, dlt, smode, om1);
 #pragma unroll
                         for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
                     }
@@ -725,7 +814,9 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 B[2 * p + 1] = h1;
                             }
                         }
-                        const AT v = weight<AT>(gm, m0 + m);
+                        AT v;
+                        if constexpr (IsPatch2<POL>::value) v = ((ConstPtr<float>)gm.p2_vf)[m0 + m];
+                        else v = weight<AT>(gm, m0 + m);
                         const AT vom = v * (om0 + (AT)m * dlt);
                         POL::template recombine<AT>(v, vom, quant<QUANT>(cc.c), quant<QUANT>(cc.s), B, auxc, acc);
                         cc.step();
@@ -766,8 +857,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         POL::template kappa<AT>(auxo, ko);
                         POL::template fetch<AT>(a, colok && yin + 1 < H, rowc(yin + 1), jxc, rin);
                         POL::template fetch<AT>(a, colok && yout + 1 >= ylo, rowc(yout + 1), jxc, rout);
-                        ci.start(vin, auxi[0], om0, dlt, smode);
-                        co.start(vout, auxo[0], om0, dlt, smode);
+                        chain_start<POL>(ci, vin, auxi, om0, dlt, smode, om1);
+                        chain_start<POL>(co, vout, auxo, om0, dlt, smode, om1);
                         if constexpr (NSC > 0) {
 #pragma unroll
                             for (int j = 0; j < NSC; ++j) {

@@ -35,7 +35,7 @@ struct Resolved {
 
 // The kernel family a request is resolved for: its pass sizes and residency
 // set the orders per pass and the segment height.
-enum Kind { kForward = 0, kTrain = 1, kBackward = 2 };
+enum Kind { kForward = 0, kTrain = 1, kBackward = 2, kPatch2 = 3 };
 int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r,
             int kind = kForward);
 // Orders per pass from a kernel family's full pass and a smaller one (0: half

@@ -102,6 +102,7 @@ struct IO {
     float *out2;           // train: saved planes Q, E1, E2 (dense)
     int H, W;
     int pitch_in, pitch_out;
+    int uy, ux;            // two-pixel patch: offset of the second patch pixel
 };
 
 // Per-launch arguments of the single-image strip kernels.  Weights are FP64 in
@@ -123,6 +124,13 @@ struct StripArgs {
     float sp_u[kMaxSpatialFreq];
     const float *sp_row;   // (cos, sin)(nu_j y), j-major, H rows
     const float *sp_col;   // (cos, sin)(nu_j x), j-major, W columns
+    // two-pixel patch (non-local means, Section 5): orders come in groups of
+    // p2_group, one group per frequency omega_1 = p2_omega1_base + n p2_delta1
+    // of the first patch pixel, each holding the folded orders of the second;
+    // their weights (FP32, K entries) are in device memory at vf_dev
+    int p2_group;
+    double p2_omega1_base, p2_delta1;
+    const float *vf_dev;
 };
 
 // Per-launch arguments of the polynomial-kernel strip kernel.
@@ -153,6 +161,9 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int 
 hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);
+// FP32 forward of the two-pixel-patch filter (orders per pass kc, one of the
+// forward's two pass sizes for the block).
+hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 // FP32 forward with the separable spatial kernel of plan sp (nsc >= 1).
 hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, int kc, hipStream_t s,
                               int *occ = nullptr);

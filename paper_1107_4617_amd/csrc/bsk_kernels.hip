@@ -56,6 +56,10 @@ __device__ __forceinline__ Geom geom_of(const StripArgs &a)
     for (int j = 0; j < kMaxSpatialFreq; ++j) gm.sp_u[j] = a.sp_u[j];
     gm.sp_row = a.sp_row;
     gm.sp_col = a.sp_col;
+    gm.p2_group = a.p2_group;
+    gm.p2_vf = a.vf_dev;
+    gm.p2_omega1_base = a.p2_omega1_base;
+    gm.p2_delta1 = a.p2_delta1;
     return gm;
 }
 
@@ -192,6 +196,30 @@ hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, i
     if (prec == 2) return kahan ? fwd32<2, true>(a, block, kc, s, occ) : fwd32<2, false>(a, block, kc, s, occ);
     if (prec == 4) return kahan ? fwd32<4, true>(a, block, kc, s, occ) : fwd32<4, false>(a, block, kc, s, occ);
     return kahan ? fwd32<0, true>(a, block, kc, s, occ) : fwd32<0, false>(a, block, kc, s, occ);
+}
+
+// Two-pixel patch: the forward's shapes with the patch policy; the weights
+// come from the device table of the call.
+template <int BLOCK>
+static hipError_t patch2_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
+{
+    constexpr int KR = kr_f32(BLOCK), KL = kl_f32(BLOCK);
+    constexpr int MINB = BLOCK == 256 ? 3 : 0;
+    if (kc == KR) return launch<float, BLOCK, KR, KL, PolPatch2, 0, false, MINB>(a, s, occ);
+    if (kc == KR / 2) return launch<float, BLOCK, KR / 2, KL, PolPatch2, 0, false, MINB>(a, s, occ);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
+{
+    if (!occ && (!a.vf_dev || a.p2_group < kc || a.p2_group % kc != 0 || a.K % a.p2_group != 0))
+        return hipErrorInvalidValue;
+    switch (block) {
+    case 256: return patch2_block<256>(a, kc, s, occ);
+    case 512: return patch2_block<512>(a, kc, s, occ);
+    case 1024: return patch2_block<1024>(a, kc, s, occ);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int *occ)

@@ -62,11 +62,8 @@ struct ChebPair {
     }
 };
 
-// The coefficient tables are read-only for the whole launch and read at
-// workgroup-uniform addresses: through the constant address space they are
-// fetched by scalar loads into SGPRs instead of one vector load per lane.
-template <typename AT>
-using ConstPtr = const __attribute__((address_space(4))) AT *;
+// The coefficient tables are read through ConstPtr (bsk_device.h): scalar
+// loads at workgroup-uniform addresses.
 
 // One downward step of the scaled coefficient recurrence, in the variables
 // f_j = e_j for even j and f_j = e_j / c for odd j: substituting them removes

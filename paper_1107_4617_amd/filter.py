@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["bilateral", "spatial_filter", "spatial_sigma_for", "bilateral_train", "bilateral_backward",
+__all__ = ["bilateral", "nlm2", "spatial_filter", "spatial_sigma_for", "bilateral_train", "bilateral_backward",
            "bilateral_batched", "order_for", "plan_info", "poly_order_for", "poly_plan_info", "autotune",
            "BilateralFunction", "ShiftableBilateral", "release"]
 
@@ -131,6 +131,30 @@ def bilateral(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, 
     with torch.cuda.device(img.device):
         _lib.check(_lib.load().bilateral_shiftable_ex(
             ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T),
+            ctypes.c_void_p(out.data_ptr()), ctypes.byref(opt), _stream()))
+    return out
+
+
+def nlm2(img: torch.Tensor, radius: int, sigma_1: float, sigma_2: float, offset=(0, 1), T: float = 255.0,
+         N1: Optional[int] = None, N2: Optional[int] = None, weight_eps: float = 0.0, block: int = 0,
+         strip_h: int = 0, order_chunk: int = 0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Two-pixel-patch non-local means (Section 5 with p = 2): the patches {x, x + offset} are
+    compared through cos^N1(t1 / (sigma_1 sqrt N1)) cos^N2(t2 / (sigma_2 sqrt N2)) over the
+    (2r+1)^2 window.  offset = (rows, columns); N1, N2 None select N_0 of each factor."""
+    _check_image(img, "img")
+    if out is None:
+        out = torch.empty_like(img)
+    else:
+        _check_image(out, "out")
+        if out.shape != img.shape:
+            raise ValueError("out has the wrong shape")
+    H, W = img.shape
+    opt = _options(None, "fp32", weight_eps, False, block, strip_h, order_chunk)
+    uy, ux = (int(v) for v in offset)
+    with torch.cuda.device(img.device):
+        _lib.check(_lib.load().bilateral_shiftable_nlm2(
+            ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_1), float(sigma_2),
+            -1 if N1 is None else int(N1), -1 if N2 is None else int(N2), uy, ux, float(T),
             ctypes.c_void_p(out.data_ptr()), ctypes.byref(opt), _stream()))
     return out
 

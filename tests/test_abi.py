@@ -303,3 +303,35 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libbsk.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         _lib.load()
+
+
+def test_nlm2_errors(lib):
+    """Two-pixel-patch argument checks, refused before any launch."""
+    vp = ctypes.c_void_p
+    big, big2 = 1 << 40, 1 << 41
+
+    def call(s1=60.0, s2=60.0, N1=-1, N2=-1, img=big, out=big2, opt=None, T=255.0):
+        o = opt if opt is not None else _lib.Options()
+        return lib.bilateral_shiftable_nlm2(vp(img), 8, 8, 2, s1, s2, N1, N2, 0, 1, T, vp(out), ctypes.byref(o),
+                                            None)
+
+    assert call(img=0) == _lib.BSK_EINVAL
+    assert call(s2=0.0) == _lib.BSK_EINVAL
+    assert call(s1=float("nan")) == _lib.BSK_EINVAL
+    assert call(N1=1001) == _lib.BSK_ERANGE
+    assert call(s1=0.5, s2=0.5) == _lib.BSK_ERANGE     # automatic orders beyond 1000
+    o = _lib.Options()
+    o.order_mode = 1
+    assert call(opt=o) == _lib.BSK_EINVAL
+    for field, value in (("precision", _lib.BSK_BF16), ("kahan", 1), ("range_kernel", _lib.BSK_RANGE_POLY)):
+        o = _lib.Options()
+        setattr(o, field, value)
+        assert call(opt=o) == _lib.BSK_EUNSUPPORTED, field
+    o = _lib.Options()
+    o.spatial_N, o.spatial_sigma = 2, 2.0
+    assert call(opt=o) == _lib.BSK_EUNSUPPORTED
+    o = _lib.Options()
+    o.order_chunk = 5
+    assert call(opt=o) == _lib.BSK_EINVAL
+    # 31 x 16 folded orders fit; orders 1000 x 1000 do not
+    assert call(N1=1000, N2=1000) == _lib.BSK_ERANGE
