@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--kernel-only", nargs="?", const="headline", default=None,
-                    choices=["headline", "spatial", "poly", "poly_trunc"],
+                    choices=["headline", "spatial", "poly", "poly_trunc", "nlm2"],
                     help="profiling mode: run the headline forward (or the spatial-kernel or polynomial-"
                          "kernel forward at the same size) --steps times after --warmup, and a device copy "
                          "of --copy-mib MiB; print nothing but a summary line")
@@ -106,7 +106,8 @@ def main():
 
     import torch
     from paper_1107_4617_amd import (bilateral, bilateral_backward, bilateral_batched, bilateral_train,
-                                     plan_info, poly_order_for, poly_plan_info, spatial_filter, spatial_sigma_for)
+                                     nlm2, plan_info, poly_order_for, poly_plan_info, spatial_filter,
+                                     spatial_sigma_for)
     from paper_1107_4617_amd import workloads as wl
 
     dev = torch.device("cuda:0")
@@ -128,9 +129,14 @@ def main():
     # N_p = ceil(T^2 / (2 sigma_r^2)) = 37, all 75 Chebyshev coefficients or those above 1e-7
     fwd_poly = lambda: bilateral(img, radius, sigma, T, out=out, range_kernel="poly")  # noqa: E731
     fwd_poly_t = lambda: bilateral(img, radius, sigma, T, out=out, range_kernel="poly", weight_eps=1e-7)  # noqa: E731
+    # two-pixel-patch non-local means (Section 5, p = 2): patches {x, x + (0, 1)}, sigma 60 per
+    # patch pixel (N_0 = 8 each: 9 x 5 terms)
+    fwd_nlm = lambda: nlm2(img, radius, 60.0, 60.0, (0, 1), T, out=out)  # noqa: E731
     if args.kernel_only:
         if args.kernel_only == "spatial":
             fwd = fwd_sp
+        elif args.kernel_only == "nlm2":
+            fwd = fwd_nlm
         elif args.kernel_only == "poly":
             fwd = fwd_poly
         elif args.kernel_only == "poly_trunc":
@@ -214,6 +220,11 @@ def main():
                                                       "spatial_sigma": sig_s, "spatial_N": 2,
                                                       "vs_box": round(mean_ms / ms_sp, 3)}
         variants["algorithm1_q2_rect4096_r20"] = {"Mpixel/s": round(px / ms_a1 / 1e3, 2), "ms": round(ms_a1, 4)}
+        log("timing two-pixel-patch non-local means")
+        ms_nl, _, _ = time_calls(fwd_nlm, max(5, args.steps // 5), max(2, args.warmup // 5), stream)
+        ms_b60, _, _ = time_calls(lambda: bilateral(img, radius, 60.0, T, out=out), args.steps, args.warmup, stream)
+        variants["nlm2_patch_u01_s60_rect4096_r20"] = {"Mpixel/s": round(px / ms_nl / 1e3, 2), "ms": round(ms_nl, 4),
+                                                       "terms": 45, "bilateral_s60_ms": round(ms_b60, 4)}
         log("timing polynomial range kernel")
         n_p = poly_order_for(sigma, T)
         for name, fn, eps_p in (("poly_pN37_rect4096_r20_s30", fwd_poly, 0.0),
