@@ -18,9 +18,9 @@
 // of the raised-cosine kernel (stages V, H and R with the same LDS layout and
 // software pipeline, see bsk_device.h), and the per-pixel work that depends on
 // c is the coefficient recurrence: the d_k(c) come out of a five-term
-// recurrence in k run downwards from d_2N (bsk_plan.cpp), about seven
-// multiply-adds per coefficient.  The channels come from the three-term
-// recurrence T_{k+1} = 2 x T_k - T_{k-1}, one multiply-add per value.
+// recurrence in k run downwards from d_2N (bsk_plan.cpp), six multiply-adds
+// per coefficient.  The channels come from the three-term recurrence
+// T_{k+1} = 2 x T_k - T_{k-1}, one multiply-add per value.
 #include "bsk_device.h"
 
 namespace bsk {
