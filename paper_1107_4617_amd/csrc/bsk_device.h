@@ -497,6 +497,35 @@ constexpr int row_stride(int block, int ch, int g)
     return rs;
 }
 
+// XCD-aware tile order.  The chip's 256 CUs sit in 8 XCDs, each with its own
+// L2, and workgroups are dispatched to the XCDs round-robin by linear index.
+// The strip kernels are launched one-dimensionally: workgroup L takes tile
+// T = (L mod 8) * per + L / 8 (per = ceil(tiles / 8)), so each XCD works
+// through a contiguous run of tiles, numbered strip-fastest (row-major over
+// the segments).  Vertically adjacent segments, which share the 2r rows of
+// the window, are then one row of tiles apart on the same XCD and resident
+// together, and horizontally adjacent strips, which share the halo columns,
+// are neighbours; each XCD still spans the image's whole width.  The up to
+// seven workgroups past the last tile return at once.
+constexpr int kXcd = 8;
+__device__ __forceinline__ bool xcd_tile(int strips, int segs, int *bx, int *by)
+{
+    const int ntiles = strips * segs;
+    const int per = (ntiles + kXcd - 1) / kXcd;
+    const int L = blockIdx.x;
+    const int T = (L % kXcd) * per + L / kXcd;
+    if (T >= ntiles) return false;
+    *by = T / strips;
+    *bx = T - *by * strips;
+    return true;
+}
+// Launch size of xcd_tile's grid for a strips x segs tiling.
+inline unsigned xcd_grid(long long strips, long long segs)
+{
+    const long long ntiles = strips * segs;
+    return (unsigned)(((ntiles + kXcd - 1) / kXcd) * kXcd);
+}
+
 // Floor division and the matching non-negative remainder, for the (possibly
 // negative) interval offsets of the pipeline stages.
 constexpr int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }

@@ -68,8 +68,10 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, K
     strip_kernel(const StripArgs a)
 {
     __shared__ __align__(16) AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
+    int bx, by;
+    if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
     const Geom gm = geom_of(a);
-    strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, blockIdx.x, blockIdx.y, lds, nullptr, nullptr);
+    strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, bx, by, lds, nullptr, nullptr);
 }
 
 // FP32 forward with the separable spatial kernel (NSC non-zero frequencies,
@@ -83,9 +85,11 @@ template <int BLOCK, int KR, int NSC, bool SEVEN>
 __global__ void __launch_bounds__(BLOCK, (spatial_minb<BLOCK, NSC, SEVEN>())) spatial_kernel(const StripArgs a)
 {
     __shared__ __align__(16) float lds[strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>()];
+    int bx, by;
+    if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
     const Geom gm = geom_of(a);
-    strip_body<float, BLOCK, KR, 1, PolForward<float>, 0, false, NSC, SEVEN>(a.io, gm, blockIdx.x, blockIdx.y,
-                                                                             lds, nullptr, nullptr);
+    strip_body<float, BLOCK, KR, 1, PolForward<float>, 0, false, NSC, SEVEN>(a.io, gm, bx, by, lds, nullptr,
+                                                                             nullptr);
 }
 
 // Phase table of the spatial kernel: (cos, sin)(nu_j y) for y < n, the angle
@@ -109,9 +113,11 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward
 {
     __shared__ __align__(16) float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
     __shared__ double red_lds[BLOCK];
+    int bx, by;
+    if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
     const Geom gm = geom_of(a);
-    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(
-        a.io, gm, blockIdx.x, blockIdx.y, lds, red_lds, a.red + (blockIdx.y * gridDim.x + blockIdx.x));
+    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(a.io, gm, bx, by, lds, red_lds,
+                                                            a.red + ((long)by * a.strips + bx));
 }
 
 // Fixed-order sum of the per-workgroup partials: grad_sigma = -(1/sigma) sum.
@@ -147,7 +153,8 @@ static hipError_t launch(const StripArgs &a, hipStream_t s, int *occ)
     if (occ) return query_occupancy((const void *)strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB>, BLOCK, occ);
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
-    dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
+    if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
+    const dim3 grid(xcd_grid(a.strips, (a.io.H + a.S - 1) / a.S));
     hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -248,7 +255,8 @@ static hipError_t bwd(const StripArgs &a, hipStream_t s, int *occ)
     if (occ) return query_occupancy((const void *)backward_kernel<BLOCK, KR, KL, MINB>, BLOCK, occ);
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
-    dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
+    if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
+    const dim3 grid(xcd_grid(a.strips, (a.io.H + a.S - 1) / a.S));
     hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -286,7 +294,8 @@ static hipError_t spatial_launch(const StripArgs &a, hipStream_t s, int *occ)
     if (occ) return query_occupancy((const void *)spatial_kernel<BLOCK, KR, NSC, SEVEN>, BLOCK, occ);
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
-    dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
+    if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
+    const dim3 grid(xcd_grid(a.strips, (a.io.H + a.S - 1) / a.S));
     hipLaunchKernelGGL((spatial_kernel<BLOCK, KR, NSC, SEVEN>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }

@@ -414,7 +414,9 @@ template <typename AT, int BLOCK, int KR, int KL, bool MULTI>
 __global__ void __launch_bounds__(BLOCK, (poly_minb<AT, BLOCK, KL>())) poly_kernel(const PolyArgs a)
 {
     __shared__ __align__(16) AT lds[strip_lds_elems<2, KL, BLOCK>()];
-    poly_body<AT, BLOCK, KR, KL, MULTI>(a, blockIdx.x, blockIdx.y, lds);
+    int bx, by;
+    if (!xcd_tile((a.io.W + BLOCK - 2 * a.rh - 1) / (BLOCK - 2 * a.rh), (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
+    poly_body<AT, BLOCK, KR, KL, MULTI>(a, bx, by, lds);
 }
 
 template <typename AT, int BLOCK, int KR, int KL>
@@ -431,7 +433,7 @@ static hipError_t poly_launch(const PolyArgs &a, hipStream_t s, int *occ)
     if (Wt < 1 || a.S < 1 || a.NP < KR || a.NP % KR != 0) return hipErrorInvalidValue;
     const bool multi = a.NP > KR;
     if (multi && !a.ws) return hipErrorInvalidValue;
-    dim3 grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S);
+    const dim3 grid(xcd_grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S));
     if (multi) hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, true>), grid, dim3(BLOCK), 0, s, a);
     else hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, false>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
