@@ -335,3 +335,13 @@ def test_nlm2_errors(lib):
     assert call(opt=o) == _lib.BSK_EINVAL
     # 31 x 16 folded orders fit; orders 1000 x 1000 do not
     assert call(N1=1000, N2=1000) == _lib.BSK_ERANGE
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU; --gpus above 1 exits with a message before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr

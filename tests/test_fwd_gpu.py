@@ -75,6 +75,7 @@ def test_smooth256_fp64_and_fp32():
     ((60, 90), 6, 2, 120.0, 0, 0),          # N = 2
     ((80, 600), 70, 30, 30.0, 512, 20),     # 512-lane strips
     ((40, 1100), 200, 30, 30.0, 1024, 0),   # 1024-lane strips
+    ((12, 1100), 500, 30, 30.0, 0, 0),      # the largest clamped radius (BSK_MAX_RADIUS)
 ])
 def test_shapes_and_edge_cases(shape, r, N, sigma, block, strip_h):
     """Orders at or above N_0(sigma_r, 255), where the kernel is a valid (non-negative) kernel."""
