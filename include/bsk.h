@@ -147,7 +147,8 @@ int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_
  * img/out are float* for BSK_FP32/BF16/FP16/I16 and double* for BSK_FP64.
  * opt may be NULL (defaults).  If opt->weight_eps > 0, folded orders whose
  * unfolded weight is below it are dropped (Section 3.1); the dropped mass is
- * reported by bsk_plan_info().
+ * reported by bsk_plan_info().  A weight_eps that drops every order is
+ * BSK_EINVAL (the filter would be 0/0).
  */
 int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigma_r, float T,
                            void *out, const bsk_options *opt, void *stream);
@@ -168,8 +169,12 @@ int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigm
  *   N1, N2:    orders, or < 0 for N_0(sigma_k, T); at most 1000 each
  *   opt:       NULL or options with order_mode 0, FP32, no compensation, the
  *              box spatial kernel and the raised cosine; weight_eps > 0 drops
- *              terms of either factor whose binomial weight is below it;
+ *              terms of either factor whose binomial weight is below it
+ *              (BSK_EINVAL if that drops every term of a factor);
  *              pitches, block, strip_h and order_chunk as for the forward
+ * When the second pixel's folded orders fit in one pass of order_chunk
+ * orders, several first-pixel terms share each pass; otherwise each spans
+ * whole passes of its own.
  * Asynchronous on `stream`.  BSK_ERANGE when more than 65536 terms remain.
  */
 int bilateral_shiftable_nlm2(const float *img, int H, int W, int radius, float sigma_1, float sigma_2, int N1,

@@ -164,7 +164,7 @@ static int kernel_occupancy(const Resolved &r, int kind)
     std::memset(&a, 0, sizeof(a));
     int occ = 1;
     if (kind == kPatch2) {
-        (void)bsk::launch_patch2_f32(a, r.block, r.kc, nullptr, &occ);
+        (void)bsk::launch_patch2_f32(a, r.block, r.kc, 0, nullptr, &occ);
     } else if (r.range_kernel == BSK_RANGE_POLY) {
         bsk::PolyArgs pa;
         std::memset(&pa, 0, sizeof(pa));
@@ -252,6 +252,7 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         if (bsk::make_plan(r->N, sigma_r, o.weight_eps, &r->plan) != 0)
             return fail(BSK_ERANGE, "order N=%d leaves more than %d folded orders (raise weight_eps)", r->N,
                         bsk::kMaxOrders);
+        if (r->plan.K == 0) return fail(BSK_EINVAL, "weight_eps %g drops every order of N=%d", o.weight_eps, r->N);
     }
 
     // Clamping the radius to the image leaves every truncated window unchanged
@@ -601,20 +602,32 @@ int nlm2_impl(const float *img, int H, int W, int radius, float sigma_1, float s
     if (bsk::make_plan(n2, sigma_2, o.weight_eps, &p2) != 0)
         return fail(BSK_ERANGE, "order N2=%d leaves more than %d folded orders", n2, bsk::kMaxOrders);
     const int K1 = (int)w1.size(), K2 = p2.K;
-    int kc = r.kc;
+    if (K1 == 0 || K2 == 0) return fail(BSK_EINVAL, "weight_eps %g drops every term", o.weight_eps);
+    // Layout of the K1 x K2 terms over passes of kc orders.  Unpacked, each
+    // first-pixel term spans ceil(K2 / kc) passes of its own.  Packed (256-lane
+    // strips, 16-order passes, K2 <= 8), floor(16 / K2) whole terms share each
+    // pass and the chains restart between them.
+    const int full = bsk::chunk_forward_f32(r.block);
+    auto unpacked = [&](int c) { return (long long)K1 * ((K2 + c - 1) / c); };
+    auto cost = [&](long long np, int c) { return (double)np * (c + 2.5 + 0.1 * c); };
+    const bool can_pack = r.block == 256 && full == bsk::kPatchPackPass && K2 <= bsk::kPatchPackMax;
+    const int gpp = can_pack ? full / K2 : 0;
+    const long long np_packed = can_pack ? (K1 + gpp - 1) / gpp : 0;
+    int kc = r.kc, pack = 0;
     if (o.order_chunk == 0) {
-        // pass size: a pass stays within one first-pixel term
-        const int full = bsk::chunk_forward_f32(r.block);
-        auto cost = [&](int c) { return (double)K1 * ((K2 + c - 1) / c) * (c + 2.5 + 0.1 * c); };
-        kc = cost(full / 2) < cost(full) ? full / 2 : full;
+        kc = cost(unpacked(full / 2), full / 2) < cost(unpacked(full), full) ? full / 2 : full;
+        if (can_pack && cost(np_packed, full) <= cost(unpacked(kc), kc)) kc = full;
     }
-    const int G2 = (K2 + kc - 1) / kc * kc;
-    const long long K = (long long)K1 * G2;
+    if (can_pack && kc == full) pack = K2;
+    const int G2 = pack ? K2 : (K2 + kc - 1) / kc * kc;
+    const long long K = pack ? np_packed * kc : (long long)K1 * G2;
     if (K > 65536) return fail(BSK_ERANGE, "%lld patch orders (raise weight_eps or the sigmas)", K);
     std::vector<unsigned char> tab((size_t)K * sizeof(float), 0);
     float *vf = (float *)tab.data();
-    for (int g = 0; g < K1; ++g)
-        for (int m = 0; m < K2; ++m) vf[(size_t)g * G2 + m] = (float)(w1[g] * p2.v[m]);
+    for (int g = 0; g < K1; ++g) {
+        const size_t base = pack ? (size_t)(g / gpp) * kc + (size_t)(g % gpp) * K2 : (size_t)g * G2;
+        for (int m = 0; m < K2; ++m) vf[base + m] = (float)(w1[g] * p2.v[m]);
+    }
     void *dtab = nullptr;
     st = upload_table(stream, 7, tab, &dtab);
     if (st) return st;
@@ -649,7 +662,7 @@ int nlm2_impl(const float *img, int H, int W, int radius, float sigma_1, float s
         if (st) return st;
         a.ws = ws;
     }
-    hipError_t e = bsk::launch_patch2_f32(a, r.block, kc, (hipStream_t)stream);
+    hipError_t e = bsk::launch_patch2_f32(a, r.block, kc, pack, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "two-pixel-patch launch");
     return BSK_OK;
 }

@@ -67,6 +67,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         bsk::Plan pl;
         if (bsk::make_plan(N, q.sigma_r, o.weight_eps, &pl) != 0)
             return fail(BSK_ERANGE, "descriptor %d: order %d has too many folded orders", b, N);
+        if (pl.K == 0) return fail(BSK_EINVAL, "descriptor %d: weight_eps drops every order", b);
         std::memset(&it.im, 0, sizeof(it.im));
         it.im.img = q.img;
         it.im.out = q.out;

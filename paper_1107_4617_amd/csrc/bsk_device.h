@@ -39,6 +39,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "bsk_internal.h"
 
@@ -157,6 +158,46 @@ struct Chain {
     }
 };
 
+// The chain of a two-pixel-patch pass: phases omega_1 g_1 + (omega_0 + m delta) g_2
+// of one first-pixel frequency omega_1.  A pass may hold several first-pixel
+// frequencies, omega_1 + j delta_1, each with the same run of second-pixel
+// orders; the chain then restarts at the next frequency's first order by
+// rotating that frequency's starting phase by delta_1 g_1 (one complex
+// multiplication), with no further sincos.
+template <typename AT>
+struct PatchChain : Chain<AT> {
+    AT gc, gs;     // (cos, sin) of the current frequency's starting phase
+    AT r1c, r1s;   // (cos, sin)(delta_1 g_1)
+    AT sd;         // sin(delta g_2)
+    // start at phase psi with steps d2 = delta g_2 (orders) and d1 = delta_1 g_1
+    // (first-pixel frequencies)
+    __device__ __forceinline__ void start_patch(bool valid, AT psi, AT d2, AT d1)
+    {
+        AT c0, s0, cd;
+        sc(psi, &s0, &c0);
+        sc(d2, &sd, &cd);
+        sc(d1, &r1s, &r1c);
+        const AT z = valid ? AT(1) : AT(0);
+        this->c = gc = z * c0;
+        this->s = gs = z * s0;
+        this->cp = z * (c0 * cd + s0 * sd);
+        this->sp = z * (s0 * cd - c0 * sd);
+        this->a2 = AT(2) * cd;
+    }
+    __device__ __forceinline__ void restart()
+    {
+        const AT nc = fmat(gc, r1c, -gs * r1s);
+        const AT ns = fmat(gs, r1c, gc * r1s);
+        gc = nc;
+        gs = ns;
+        const AT cd = AT(0.5) * this->a2;
+        this->c = nc;
+        this->s = ns;
+        this->cp = fmat(nc, cd, ns * sd);
+        this->sp = fmat(ns, cd, -nc * sd);
+    }
+};
+
 template <typename T>
 __device__ __forceinline__ T ld(const void *p, long idx) { return ((const T *)p)[idx]; }
 
@@ -227,8 +268,13 @@ struct PolForward {
 // psi(z) = omega_1 g(z) + omega_2 g(z + u) in place of omega g(z); the second
 // patch pixel lies beyond the image only through the clamped read (the image
 // extended by its nearest border pixel).
-struct PolPatch2 {
+// G > 0 packs KR / G first-pixel frequencies of G orders each into every pass
+// (their chains restart at orders G, 2G, ..); G = 0 runs one frequency's
+// orders per pass range.
+template <int G>
+struct PolPatch2G {
     static constexpr int NCH = 4, NACC = 2, NAUX = 2, NRAW = 2, NPAIR = 2;
+    static constexpr int GROUP = G;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
     {
@@ -272,22 +318,50 @@ template <class P>
 struct IsPatch2 {
     static constexpr bool value = false;
 };
-template <>
-struct IsPatch2<PolPatch2> {
+template <int G>
+struct IsPatch2<PolPatch2G<G>> {
     static constexpr bool value = true;
+};
+using PolPatch2 = PolPatch2G<0>;
+
+// The chain type of a policy: the patch's restartable chain, else the plain one.
+template <class POL, typename AT>
+struct ChainOf {
+    using type = Chain<AT>;
+};
+template <int G, typename AT>
+struct ChainOf<PolPatch2G<G>, AT> {
+    using type = typename std::conditional<(G > 0), PatchChain<AT>, Chain<AT>>::type;
 };
 
 // Start of an order chain: the angle omega g of one value, or for the
 // two-pixel patch the phase omega_1 g_1 + omega_2 g_2 (om1 = omega_1) with the
-// step delta g_2 of the second value.
-template <class POL, typename AT>
-__device__ __forceinline__ void chain_start(Chain<AT> &ch, bool valid, const AT *aux, AT om0, AT dlt, int mode,
-                                            AT om1)
+// step delta g_2 of the second value and, when a pass holds several first-pixel
+// frequencies, the rotation by delta_1 g_1 between them (d1 = delta_1).
+template <class POL, typename AT, class CH>
+__device__ __forceinline__ void chain_start(CH &ch, bool valid, const AT *aux, AT om0, AT dlt, int mode, AT om1,
+                                            AT d1)
 {
-    if constexpr (IsPatch2<POL>::value)
-        ch.start(valid, AT(1), fmat(om1, aux[0], om0 * aux[1]), dlt * aux[1], 2);
-    else
+    if constexpr (IsPatch2<POL>::value) {
+        if constexpr (POL::GROUP > 0)
+            ch.start_patch(valid, fmat(om1, aux[0], om0 * aux[1]), dlt * aux[1], d1 * aux[0]);
+        else
+            ch.start(valid, AT(1), fmat(om1, aux[0], om0 * aux[1]), dlt * aux[1], 2);
+    } else {
         ch.start(valid, aux[0], om0, dlt, mode);
+    }
+}
+
+// Before order m of a pass (m a constant of the unrolled loops): a packed patch
+// chain moves on to the next first-pixel frequency at every multiple of G.
+template <class POL, class CH>
+__device__ __forceinline__ void chain_restart(CH &ch, int m)
+{
+    if constexpr (IsPatch2<POL>::value) {
+        if constexpr (POL::GROUP > 0) {
+            if (m > 0 && m % POL::GROUP == 0) ch.restart();
+        }
+    }
 }
 
 // Training forward: channels (C, S, gC, gS, g^2 C, g^2 S); accumulators
@@ -436,8 +510,8 @@ struct Geom {
     float sp_u[kMaxSpatialFreq];
     const float *sp_row;
     const float *sp_col;
-    // two-pixel patch: orders per first-pixel frequency, those frequencies,
-    // and the weights (device memory)
+    // two-pixel patch: orders per first-pixel frequency (unpacked layout),
+    // those frequencies, and the weights (device memory)
     int p2_group;
     double p2_omega1_base, p2_delta1;
     const float *p2_vf;
@@ -681,13 +755,22 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
         AT om0 = (AT)(gm.omega_base + (double)m0 * gm.delta);
         const AT dlt = (AT)gm.delta;
         const int smode = first ? gm.start_mode : 2;
-        AT om1 = AT(0);
+        AT om1 = AT(0), d1 = AT(0);
         if constexpr (IsPatch2<POL>::value) {
-            // a pass lies within one group: its first-pixel frequency, and the
-            // second pixel's frequency of its first order
-            const int n1 = m0 / gm.p2_group;
+            // the first-pixel frequency of the pass's first order and the second
+            // pixel's frequency of that order: either the pass holds KR / G whole
+            // groups, each from the second pixel's first order, or it lies within
+            // one group of p2_group orders
+            int n1;
+            if constexpr (POL::GROUP > 0) {
+                n1 = (m0 / KR) * (KR / POL::GROUP);
+                om0 = (AT)gm.omega_base;
+            } else {
+                n1 = m0 / gm.p2_group;
+                om0 = (AT)(gm.omega_base + (double)(m0 - n1 * gm.p2_group) * gm.delta);
+            }
             om1 = (AT)(gm.p2_omega1_base + (double)n1 * gm.p2_delta1);
-            om0 = (AT)(gm.omega_base + (double)(m0 - n1 * gm.p2_group) * gm.delta);
+            d1 = (AT)gm.p2_delta1;
         }
 
         AT V[KR][NCH];
@@ -725,10 +808,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         }
                     }
                 }
-                Chain<AT> ch;
-                chain_start<POL>(ch, colok, aux, om0, dlt, smode, om1);
+                typename ChainOf<POL, AT>::type ch;
+                chain_start<POL>(ch, colok, aux, om0, dlt, smode, om1, d1);
 #pragma unroll
                 for (int m = 0; m < KR; ++m) {
+                    chain_restart<POL>(ch, m);
                     const AT C = quant<QUANT>(ch.c), S = quant<QUANT>(ch.s);
 #pragma unroll
                     for (int p = 0; p < NPAIR; ++p) {
@@ -760,7 +844,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
             POL::template fetch<AT>(a, colok && yout >= ylo, rowc(yout), jxc, rout);
             POL::template fetch<AT>(a, colok, i0, jxc, rc);
         }
-        Chain<AT> ci, co, cc;
+        typename ChainOf<POL, AT>::type ci, co, cc;
         AT ki[NPAIR], ko[NPAIR], auxc[NAUX], acc[NACC];
         // spatial kernel: kappa times the phases of the incoming and outgoing
         // rows, and u_j (cos, sin)(nu_j i) of the output row
@@ -806,7 +890,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     if (sR == 0) {
                         POL::template make<AT>(rc, ref, auxc);
                         POL::template fetch<AT>(a, colok, rowc(iR + 1), jxc, rc);
-                        chain_start<POL>(cc, colok, auxc, om0, dlt, smode, om1);
+                        chain_start<POL>(cc, colok, auxc, om0, dlt, smode, om1, d1);
 #pragma unroll
                         for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
                     }
@@ -843,6 +927,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 B[2 * p + 1] = h1;
                             }
                         }
+                        chain_restart<POL>(cc, m);
                         AT v;
                         if constexpr (IsPatch2<POL>::value) v = ((ConstPtr<float>)gm.p2_vf)[m0 + m];
                         else v = weight<AT>(gm, m0 + m);
@@ -886,8 +971,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         POL::template kappa<AT>(auxo, ko);
                         POL::template fetch<AT>(a, colok && yin + 1 < H, rowc(yin + 1), jxc, rin);
                         POL::template fetch<AT>(a, colok && yout + 1 >= ylo, rowc(yout + 1), jxc, rout);
-                        chain_start<POL>(ci, vin, auxi, om0, dlt, smode, om1);
-                        chain_start<POL>(co, vout, auxo, om0, dlt, smode, om1);
+                        chain_start<POL>(ci, vin, auxi, om0, dlt, smode, om1, d1);
+                        chain_start<POL>(co, vout, auxo, om0, dlt, smode, om1, d1);
                         if constexpr (NSC > 0) {
 #pragma unroll
                             for (int j = 0; j < NSC; ++j) {
@@ -910,6 +995,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
 #pragma unroll
                     for (int k = 0; k < KL; ++k) {
                         const int m = h * KL + k;
+                        chain_restart<POL>(ci, m);
+                        chain_restart<POL>(co, m);
                         const AT Ci = quant<QUANT>(ci.c), Si = quant<QUANT>(ci.s);
                         const AT Co = quant<QUANT>(co.c), So = quant<QUANT>(co.s);
 #pragma unroll

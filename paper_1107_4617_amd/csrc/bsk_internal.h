@@ -124,10 +124,16 @@ struct StripArgs {
     float sp_u[kMaxSpatialFreq];
     const float *sp_row;   // (cos, sin)(nu_j y), j-major, H rows
     const float *sp_col;   // (cos, sin)(nu_j x), j-major, W columns
-    // two-pixel patch (non-local means, Section 5): orders come in groups of
-    // p2_group, one group per frequency omega_1 = p2_omega1_base + n p2_delta1
-    // of the first patch pixel, each holding the folded orders of the second;
-    // their weights (FP32, K entries) are in device memory at vf_dev
+    // two-pixel patch (non-local means, Section 5): the orders of one frequency
+    // omega_1 = p2_omega1_base + n p2_delta1 of the first patch pixel are the
+    // folded orders of the second, laid out in one of two ways (the launch's
+    // pack argument):
+    //   pack = 0: group n holds p2_group orders (a multiple of the pass size,
+    //     zero-weighted beyond the folded ones) and a pass lies within a group;
+    //   pack = G > 0: each pass of KR orders holds KR / G groups of G orders,
+    //     n = pass (KR / G) + j at positions j G .. j G + G - 1, zero weights
+    //     beyond the last group.
+    // The weights (FP32, K entries) are in device memory at vf_dev.
     int p2_group;
     double p2_omega1_base, p2_delta1;
     const float *vf_dev;
@@ -162,8 +168,11 @@ hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *o
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);
 // FP32 forward of the two-pixel-patch filter (orders per pass kc, one of the
-// forward's two pass sizes for the block).
-hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
+// forward's two pass sizes for the block; pack = 0 or the group size G of the
+// packed layout, which needs the 256-lane block and kc = kPatchPackPass).
+constexpr int kPatchPackPass = 16;
+constexpr int kPatchPackMax = 8;
+hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, int pack, hipStream_t s, int *occ = nullptr);
 // FP32 forward with the separable spatial kernel of plan sp (nsc >= 1).
 hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, int kc, hipStream_t s,
                               int *occ = nullptr);

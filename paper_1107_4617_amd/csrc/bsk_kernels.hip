@@ -217,8 +217,27 @@ static hipError_t patch2_block(const StripArgs &a, int kc, hipStream_t s, int *o
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
+// Packed layout: the 256-lane full pass with groups of G orders, G = pack.
+template <int G>
+static hipError_t patch2_packed(const StripArgs &a, int pack, hipStream_t s, int *occ)
 {
+    if constexpr (G == 0) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int KR = kr_f32(256), KL = kl_f32(256);
+        if (pack == G) return launch<float, 256, KR, KL, PolPatch2G<G>, 0, false, 3>(a, s, occ);
+        return patch2_packed<G - 1>(a, pack, s, occ);
+    }
+}
+
+hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, int pack, hipStream_t s, int *occ)
+{
+    static_assert(kr_f32(256) == kPatchPackPass, "packed patch kernels use the 256-lane full pass");
+    if (pack != 0) {
+        if (block != 256 || kc != kPatchPackPass || pack < 1 || pack > kPatchPackMax) return hipErrorInvalidValue;
+        if (!occ && (!a.vf_dev || a.K % kc != 0)) return hipErrorInvalidValue;
+        return patch2_packed<kPatchPackMax>(a, pack, s, occ);
+    }
     if (!occ && (!a.vf_dev || a.p2_group < kc || a.p2_group % kc != 0 || a.K % a.p2_group != 0))
         return hipErrorInvalidValue;
     switch (block) {

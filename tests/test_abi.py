@@ -335,6 +335,24 @@ def test_nlm2_errors(lib):
     assert call(opt=o) == _lib.BSK_EINVAL
     # 31 x 16 folded orders fit; orders 1000 x 1000 do not
     assert call(N1=1000, N2=1000) == _lib.BSK_ERANGE
+    o = _lib.Options()
+    o.weight_eps = 0.9   # above every binomial weight of N = 8: nothing would be left
+    assert call(opt=o) == _lib.BSK_EINVAL
+
+
+def test_weight_eps_dropping_every_order_is_refused(lib):
+    """A weight_eps above the central binomial weight would leave no order (the filter 0/0):
+    refused before any launch, by the single-image and the batched entry points."""
+    vp = ctypes.c_void_p
+    o = _lib.Options()
+    o.order_mode, o.N, o.weight_eps = 1, 30, 0.5      # the central weight of N = 30 is 0.144
+    assert lib.bilateral_shiftable_ex(vp(1 << 40), 8, 8, 2, 30.0, 255.0, vp(1 << 41), ctypes.byref(o),
+                                      None) == _lib.BSK_EINVAL
+    d = _lib.ImageDesc()
+    d.img, d.out, d.H, d.W, d.radius, d.sigma_r, d.N = 1 << 40, 1 << 41, 8, 8, 2, 30.0, 30
+    assert lib.bilateral_shiftable_batched(ctypes.byref(d), 1, 255.0, ctypes.byref(o), None) == _lib.BSK_EINVAL
+    k = ctypes.c_int()                                 # 0.14 keeps only the central order (0.135 next)
+    assert lib.bsk_plan_info(30, 0.14, ctypes.byref(k), None) == _lib.BSK_OK and k.value == 1
 
 
 def test_bench_refuses_several_gpus():

@@ -45,6 +45,9 @@ CASES = [
     ((57, 99), 4, 60.0, 40.0, (0, -1), 9, 25, {}),                # odd first order, 13 folded second
     ((40, 90), 6, 60.0, 60.0, (3, 3), None, None, {"order_chunk": 16}),
     ((40, 90), 6, 60.0, 60.0, (3, 3), None, None, {"order_chunk": 8}),
+    ((45, 77), 4, 60.0, 60.0, (0, 1), 8, 14, {}),                 # packed, 2 groups of 8 per pass, ragged last
+    ((45, 77), 4, 60.0, 60.0, (1, -1), 5, 45, {"order_chunk": 16}),  # 23 folded: a term spans two passes
+    ((38, 70), 5, 60.0, 60.0, (0, 1), 12, 5, {}),                 # packed, 5 groups of 3 per pass
     ((60, 600), 100, 60.0, 60.0, (0, 2), None, None, {}),         # 512-lane strips
     ((30, 1100), 300, 80.0, 80.0, (1, 1), None, None, {}),        # 1024-lane strips
     ((1, 200), 4, 60.0, 60.0, (0, 1), None, None, {}),            # one row
