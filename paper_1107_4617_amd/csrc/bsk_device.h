@@ -211,10 +211,13 @@ __device__ __forceinline__ T ld(const void *p, long idx) { return ((const T *)p)
 // Channels come in pairs (kappa_p C, kappa_p S) with a per-pixel coefficient
 // kappa_p; channel 2p is the cosine member and 2p+1 the sine member.
 
-// Forward: channels (C, S, gC, gS), g = f - ref; accumulators (Q, P).
-template <typename FT>
+// Forward: channels (C, S, gC, gS), g = f - ref; accumulators (Q, P).  SM >= 0
+// fixes a one-pass launch (K <= KR) whose chain start mode is SM (0: even N,
+// 1: odd N), so the start's selects and the general-angle path compile away.
+template <typename FT, int SM = -1>
 struct PolForward {
     static constexpr int NCH = 4, NACC = 2, NAUX = 1, NRAW = 1, NPAIR = 2;
+    static constexpr int START = SM;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
     {
@@ -274,6 +277,7 @@ struct PolForward {
 template <int G>
 struct PolPatch2G {
     static constexpr int NCH = 4, NACC = 2, NAUX = 2, NRAW = 2, NPAIR = 2;
+    static constexpr int START = -1;
     static constexpr int GROUP = G;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
@@ -371,6 +375,7 @@ __device__ __forceinline__ void chain_restart(CH &ch, int m)
 // planes Q, E1 = A1 - (u-ref) A0, E2 = A2 - (g_z + u - ref) A1 + g_z (u-ref) A0.
 struct PolTrain {
     static constexpr int NCH = 6, NACC = 5, NAUX = 1, NRAW = 1, NPAIR = 3;
+    static constexpr int START = -1;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
     {
@@ -440,6 +445,7 @@ struct PolTrain {
 // alpha(x) E2(x) feed dL/dsigma_r.
 struct PolBackward {
     static constexpr int NCH = 4, NACC = 1, NAUX = 3, NRAW = 4, NPAIR = 2;
+    static constexpr int START = -1;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
     {
@@ -749,12 +755,15 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
 
     double red = 0.0;
 
-    for (int m0 = 0; m0 < gm.K; m0 += KR) {
+    // POL::START >= 0: one pass (K <= KR) whose chain start mode is that constant
+    constexpr int CSTART = POL::START;
+    const int Kloop = CSTART >= 0 ? 1 : gm.K;
+    for (int m0 = 0; m0 < Kloop; m0 += KR) {
         const bool first = (m0 == 0);
-        const bool last = (m0 + KR >= gm.K);
+        const bool last = CSTART >= 0 || (m0 + KR >= gm.K);
         AT om0 = (AT)(gm.omega_base + (double)m0 * gm.delta);
         const AT dlt = (AT)gm.delta;
-        const int smode = first ? gm.start_mode : 2;
+        const int smode = first ? (CSTART >= 0 ? CSTART : gm.start_mode) : 2;
         AT om1 = AT(0), d1 = AT(0);
         if constexpr (IsPatch2<POL>::value) {
             // the first-pixel frequency of the pass's first order and the second
@@ -944,8 +953,10 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     if (walker) {
 #pragma unroll
                         for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
+                        // local exclusive prefixes: loc[u] = sum_{v < u} of the chunk (loc[0] = 0 is implicit)
+                        run = loc[0];
 #pragma unroll
-                        for (int u = 0; u < G; ++u) {
+                        for (int u = 1; u < G; ++u) {
                             const AT x = loc[u];
                             loc[u] = run;
                             run += x;
@@ -953,8 +964,9 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     }
                     const AT off = group_exclusive_scan<CH>(run, wch);
                     if (walker) {
+                        VbH[wbase] = off;
 #pragma unroll
-                        for (int u = 0; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
+                        for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
                     }
                 }
 
