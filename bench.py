@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6       # MI355X published FP64 vector peak
 PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 # Algorithmic FP32 work of the method per (pixel, folded order): rotation of
 # (cos, sin) 6, f-weighted channels 2, four channels x two directions x two
@@ -210,6 +211,18 @@ def main():
                                   "folded_orders": kb, "dropped_weight": eps,
                                   "max_abs_vs_fp32": float((outq - out).abs().max())}
         del outq
+        # FP64 throughout (transforms, sums, recombination) at the headline workload
+        log("timing fp64 form")
+        img64 = img.double()
+        out64 = torch.empty_like(img64)
+        ms_d, _, _ = time_calls(lambda: bilateral(img64, radius, sigma, T, N=N, precision="fp64", out=out64),
+                                max(5, args.steps // 5), max(2, args.warmup // 5), stream)
+        variants["fp64_rect4096_r20_s30"] = {"Mpixel/s": round(px / ms_d / 1e3, 2), "ms": round(ms_d, 4),
+                                             "fp64_TFLOP/s": round(px * K * FLOP_PER_PX_ORDER / (ms_d * 1e-3) / 1e12, 2),
+                                             "fp64_frac": round(px * K * FLOP_PER_PX_ORDER / (ms_d * 1e-3) / 1e12
+                                                                / PEAK_FP64_TFLOPS, 4),
+                                             "max_abs_vs_fp32": float((out64.float() - out).abs().max())}
+        del img64, out64
         # Algorithm 2 with the separable q_2 spatial kernel (M = 9) and Algorithm 1 at the
         # headline size and window
         log("timing spatial kernels")
