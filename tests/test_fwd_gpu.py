@@ -73,6 +73,8 @@ def test_smooth256_fp64_and_fp32():
     ((60, 90), 6, 1, 200.0, 0, 0),          # N = 1 (N_0 = 1 at sigma_r = 200)
     ((60, 90), 6, 7, 70.0, 0, 0),           # odd N (N_0 = 6 at sigma_r = 70)
     ((60, 90), 6, 2, 120.0, 0, 0),          # N = 2
+    ((70, 300), 8, 31, 30.0, 0, 0),         # odd N filling one 16-order pass
+    ((70, 300), 8, 29, 30.0, 256, 0),       # odd N, 15 orders in a 16-order pass
     ((80, 600), 70, 30, 30.0, 512, 20),     # 512-lane strips
     ((40, 1100), 200, 30, 30.0, 1024, 0),   # 1024-lane strips
     ((12, 1100), 500, 30, 30.0, 0, 0),      # the largest clamped radius (BSK_MAX_RADIUS)
