@@ -60,6 +60,21 @@ def test_smooth256_fp64_and_fp32():
     assert err <= TOL32, err
 
 
+@pytest.mark.parametrize("shape,r,N,sigma,block", [
+    ((70, 300), 8, 31, 30.0, 0),       # odd N, two passes of 8 orders
+    ((70, 300), 8, 7, 70.0, 0),        # odd N, one pass
+    ((60, 90), 6, 8, 60.0, 0),         # even N, one pass
+    ((129, 257), 20, 43, 25.0, 256),   # 22 orders, three passes
+    ((80, 600), 70, 30, 30.0, 512),    # 512-lane strips
+])
+def test_fp64_matches_oracle(shape, r, N, sigma, block):
+    """The FP64 path (transforms, sums and recombination in FP64) against the oracle to 1e-9 T."""
+    f = wl.rect_image(*shape, seed=7 + r)
+    ref = oracle.bilateral(f, r, sigma, N)
+    out = _gpu_filter(f.astype(np.float64), r, sigma, N=N, precision="fp64", block=block)
+    assert np.max(np.abs(out - ref)) <= TOL64
+
+
 @pytest.mark.parametrize("shape,r,N,sigma,block,strip_h", [
     ((1, 1), 3, 30, 30.0, 0, 0),
     ((1, 37), 4, 30, 30.0, 0, 0),
