@@ -67,7 +67,9 @@ def time_calls(fn, steps, warmup, stream):
     return float(np.mean(ms)), float(np.median(ms)), wall
 
 
-def cpu_baseline(img, radius, sigma, N, budget_s=12.0):
+def cpu_baseline(img, radius, sigma, N, T, gpu_out=None, budget_s=12.0):
+    """Times the FP64 oracle on a seeded sample of pixels; with the GPU output of the
+    same workload, also returns its errors against the oracle on that sample."""
     import oracle
     H, W = img.shape
     rng = np.random.default_rng(123)
@@ -79,11 +81,17 @@ def cpu_baseline(img, radius, sigma, N, budget_s=12.0):
     n = int(min(H * W, max(n0, n0 * budget_s / max(t_cal, 1e-6))))
     idx = rng.integers(0, H * W, n)
     t0 = time.perf_counter()
-    oracle.bilateral_at(img, idx, radius, sigma, N)
+    ref = oracle.bilateral_at(img, idx, radius, sigma, N)
     dt = time.perf_counter() - t0
-    return {"value": n / dt / 1e6, "unit": "Mpixel/s", "cores": oracle.num_threads(), "kind": "oracle",
+    base = {"value": n / dt / 1e6, "unit": "Mpixel/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{n} seeded random pixels of the {H}x{W} r={radius} image, direct FP64 window sums "
                       f"({(2 * radius + 1) ** 2} kernel evaluations per pixel), {dt:.1f} s"}
+    if gpu_out is None:
+        return base, None
+    err = np.abs(gpu_out.ravel()[idx].astype(np.float64) - ref)
+    parity = {"vs": "oracle", "pixels": n, "max_abs": float(err.max()), "rms": float(np.sqrt(np.mean(err ** 2))),
+              "p99.99": float(np.quantile(err, 0.9999)), "tolerance": 1e-4 * T}
+    return base, parity
 
 
 def main():
@@ -157,6 +165,8 @@ def main():
         return
     log("timing FP32 forward")
     mean_ms, med_ms, wall = time_calls(fwd, args.steps, args.warmup, stream)
+    torch.cuda.synchronize()
+    out_head = out.cpu().numpy()   # the headline output, for the oracle comparison
     px = H * W
     value = px / (mean_ms * 1e-3) / 1e6
     flops = FLOP_PER_PX_ORDER * K * px
@@ -321,7 +331,7 @@ def main():
 
     if not args.no_cpu:
         log("timing CPU oracle sample")
-        rec["cpu_baseline"] = cpu_baseline(img_np, radius, sigma, N)
+        rec["cpu_baseline"], rec["parity"] = cpu_baseline(img_np, radius, sigma, N, T, gpu_out=out_head)
     print(json.dumps(rec), flush=True)
 
 
