@@ -67,7 +67,7 @@ def time_calls(fn, steps, warmup, stream):
     return float(np.mean(ms)), float(np.median(ms)), wall
 
 
-def cpu_baseline(img, radius, sigma, N, T, gpu_out=None, budget_s=12.0):
+def cpu_baseline(img, radius, sigma, N, T, gpu_out=None, budget_s=20.0):
     """Times the FP64 oracle on a seeded sample of pixels; with the GPU output of the
     same workload, also returns its errors against the oracle on that sample."""
     import oracle
