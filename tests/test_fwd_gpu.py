@@ -211,6 +211,18 @@ def test_precision_forms_rect4096_full_image(rect4096, kahan):
         assert np.max(np.abs(out.ravel()[idx] - ref_t)) <= bound, prec
 
 
+def test_fp64_rect4096_sampled():
+    """The FP64 path at the headline workload, as bench.py times it; oracle at sampled pixels."""
+    f = wl.rect_image(4096, 4096, seed=2)
+    out = _gpu_filter(f.astype(np.float64), 20, 30.0, N=30, precision="fp64")
+    rng = np.random.default_rng(33)
+    idx = np.unique(np.concatenate([rng.integers(0, 4096 * 4096, 1500),
+                                    4095 * 4096 + rng.integers(0, 4096, 100),
+                                    rng.integers(0, 4096, 100) * 4096 + 215]))
+    ref = oracle.bilateral_at(f, idx, 20, 30.0, 30)
+    assert np.max(np.abs(out.ravel()[idx] - ref)) <= TOL64
+
+
 def test_rect8192_r32_precision_form_sampled():
     """8192x8192, r=32, sigma_r=15, N=117, weights below 1e-7 dropped (28 of 59 folded
     orders), against the oracle's truncated kernel and the exact one.  The 16-bit

@@ -89,6 +89,35 @@ def test_denoise_256_crop():
     assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
 
 
+def test_rect4096_adjoint_sampled():
+    """Training forward and adjoint at the headline workload (4096x4096 rect, r = 20, sigma_r = 30,
+    N = 30) in the launch shapes bench.py times.  dL/dimg at a pixel z depends on f and gbar only
+    within distance 2r of z, so the oracle gradient of a crop holding that neighbourhood (cut at
+    the image's own edges) equals the full image's at z."""
+    n, r, s, N = 4096, 20, 30.0, 30
+    f = wl.rect_image(n, n, seed=2)
+    g = np.random.default_rng(9).normal(size=(n, n)).astype(np.float32)
+    x = _cuda(f)
+    out, saved = bilateral_train(x, r, s, T, N)
+    gi, _ = bilateral_backward(x, _cuda(g), r, s, T, N, out=out, saved=saved)
+    torch.cuda.synchronize()
+    gi = gi.cpu().numpy()
+    rng = np.random.default_rng(10)
+    pts = [(int(a), int(b)) for a, b in rng.integers(0, n, (20, 2))]
+    pts += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (int(rng.integers(0, n)), 215),
+            (int(rng.integers(0, n)), 216), (51, int(rng.integers(0, n))), (52, int(rng.integers(0, n)))]
+    got, ref = [], []
+    m = 2 * r + 1
+    for i, j in pts:
+        i0, i1, j0, j1 = max(0, i - m), min(n, i + m + 1), max(0, j - m), min(n, j + m + 1)
+        gf, _, _ = oracle.bilateral_grad(f[i0:i1, j0:j1].astype(np.float64), g[i0:i1, j0:j1].astype(np.float64),
+                                         r, s, N)
+        ref.append(gf[i - i0, j - j0])
+        got.append(gi[i, j])
+    ref, got = np.array(ref), np.array(got)
+    assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref))
+
+
 def test_multi_pass_adjoint():
     """N = 117: 59 folded orders, several passes in both training forward and adjoint."""
     f = wl.rect_image(48, 80, seed=11, n_rect=8)

@@ -113,6 +113,38 @@ def test_spatial_large_image_sampled():
     assert np.max(np.abs(out.ravel()[idx] - ref)) <= TOL32
 
 
+def _rect4096_samples(seed):
+    rng = np.random.default_rng(seed)
+    n = 4096
+    return np.unique(np.concatenate([rng.integers(0, n * n, 2000),          # interior
+                                     (n - 1) * n + rng.integers(0, n, 150),  # last row
+                                     rng.integers(0, n, 150) * n + n - 1,    # last column
+                                     rng.integers(0, n, 150) * n + 215,      # strip edges (216 columns)
+                                     rng.integers(0, n, 150) * n + 216]))
+
+
+def test_spatial_rect4096_sampled():
+    """The separable q_2 kernel (M = 9) at the workload bench.py times: 4096x4096 rect, r = 20,
+    sigma_r = 30, N = 30, sigma_s = spatial_sigma_for(20, 2), in the default launch shape."""
+    f = wl.rect_image(4096, 4096, seed=2)
+    sigma_s = spatial_sigma_for(20, 2)
+    out = _run(f, 20, 30.0, 30, sigma_s, 2)
+    idx = _rect4096_samples(31)
+    ref = oracle.bilateral_sp_at(f, idx, 20, 30.0, 30, sigma_s, 2)
+    assert np.max(np.abs(out.ravel()[idx] - ref)) <= TOL32
+
+
+def test_algorithm1_rect4096_sampled():
+    """Algorithm 1 with the same q_2 kernel on the same 4096x4096 image, as bench.py times it."""
+    f = wl.rect_image(4096, 4096, seed=2)
+    sigma_s = spatial_sigma_for(20, 2)
+    x = torch.from_numpy(f).cuda()
+    out = spatial_filter(x, 20, sigma_s, 2).cpu().numpy().astype(np.float64)
+    idx = _rect4096_samples(32)
+    ref = oracle.bilateral_sp_at(f, idx, 20, 1.0, 0, sigma_s, 2)
+    assert np.max(np.abs(out.ravel()[idx] - ref)) <= TOL32
+
+
 def test_spatial_pitch():
     """Row pitches larger than the width: the spatial path reads and writes through them."""
     f = wl.rect_image(45, 70, seed=13)
