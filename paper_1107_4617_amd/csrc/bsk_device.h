@@ -132,6 +132,19 @@ __device__ __forceinline__ float fmat(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ void sc(double x, double *s, double *c) { sincos(x, s, c); }
 
+// sin and cos of a recurrence step d = delta g: the half angle by the
+// polynomials without reduction (|d| <= pi when the order is at least N_0 and
+// the data span at most T; beyond that sc_small reduces), then the double-angle
+// formulas.
+template <typename AT>
+__device__ __forceinline__ void sc_step(AT d, AT *s, AT *c)
+{
+    AT sh, ch;
+    sc_small(AT(0.5) * d, &sh, &ch);
+    *c = fmat(AT(-2) * sh, sh, AT(1));
+    *s = AT(2) * sh * ch;
+}
+
 // Stack quantisation of the precision forms: 1 bfloat16, 2 float16 (both round
 // to nearest even), 4 signed 16-bit fixed point with 15 fraction bits (the
 // basis values lie in [-1, 1]); 0 leaves FP32 values untouched.
@@ -169,7 +182,7 @@ struct Chain {
             s0 = mode == 0 ? AT(0) : sh;
         } else {
             sc(om0 * g, &s0, &c0);
-            sc(dlt * g, &sd, &cd);
+            sc_step(dlt * g, &sd, &cd);
         }
         const AT z = valid ? AT(1) : AT(0);
         c = z * c0;
@@ -206,8 +219,8 @@ struct PatchChain : Chain<AT> {
     {
         AT c0, s0, cd;
         sc(psi, &s0, &c0);
-        sc(d2, &sd, &cd);
-        sc(d1, &r1s, &r1c);
+        sc_step(d2, &sd, &cd);
+        sc_step(d1, &r1s, &r1c);
         const AT z = valid ? AT(1) : AT(0);
         this->c = gc = z * c0;
         this->s = gs = z * s0;
