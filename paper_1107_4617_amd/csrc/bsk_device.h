@@ -938,6 +938,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 AT *const VbH = lds + bH * BUF;
                 const V2 *const VbR = reinterpret_cast<const V2 *>(lds + bR * BUF);
 
+                // Wave priorities per stage (H above R above V): a SIMD's arbiter then
+                // issues the LDS-bound stages of the waves that have just passed the
+                // barrier ahead of the VALU-bound V stage of the others, so the
+                // barrier's critical path shortens while V fills the gaps.
+                __builtin_amdgcn_s_setprio(1);
                 // ---- R stage: box sums of the orders sR KL .. of row iR, recombined
                 if (actR && outlane) {
                     if (sR == 0) {
@@ -990,6 +995,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     }
                 }
 
+                __builtin_amdgcn_s_setprio(2);
                 // ---- H stage: every row of buffer t - 1 into its exclusive prefix sums, in place
                 if (actH) {
                     AT loc[G];
@@ -1014,6 +1020,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     }
                 }
 
+                __builtin_amdgcn_s_setprio(0);
                 // ---- V stage: vertical moving sums V += X(i + rv) - X(i - rv - 1)
                 if (actV) {
                     if (h == 0) {
