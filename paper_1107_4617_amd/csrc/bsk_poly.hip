@@ -241,6 +241,8 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                 AT *const VbH = lds + bH * BUF;
                 const V2 *const VbR = reinterpret_cast<const V2 *>(lds + bR * BUF);
 
+                // wave priorities per stage, as in the strip body (H above R above V)
+                __builtin_amdgcn_s_setprio(1);
                 // ---- R stage: coefficients of the centre value (first sub-phase),
                 //      then the box sums of the pass's channels
                 if (actR && outlane) {
@@ -332,6 +334,7 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                     }
                 }
 
+                __builtin_amdgcn_s_setprio(2);
                 // ---- H stage: every row of buffer t - 1 into its exclusive prefix sums, in place
                 if (actH) {
                     AT loc[G];
@@ -353,6 +356,7 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                     }
                 }
 
+                __builtin_amdgcn_s_setprio(0);
                 // ---- V stage: vertical moving sums V += X(i + rv) - X(i - rv - 1)
                 if (actV) {
                     if (h == 0) {
