@@ -367,14 +367,15 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     } else if (tuned_S > 0) {
         r->S = tuned_S;
     } else {
-        // Rows per workgroup: at most two full rounds of resident workgroups of
-        // the kernel that will run.  Fewer, taller workgroups leave compute
-        // units idle or without a second resident workgroup to overlap with;
-        // shorter ones repeat the 2 rv rows of window initialisation more
-        // often.  The segment count rounds down, so a last, nearly empty round
-        // of workgroups never appears.
+        // Rows per workgroup: one round of resident workgroups of the kernel
+        // that will run, so the 2 rv rows of window initialisation repeat as
+        // seldom as the chip allows while every compute unit holds its full
+        // complement.  (With the per-stage wave priorities of the strip body
+        // one round beats two by 3-5% on every strip kernel.)  The segment
+        // count rounds down, so a last, partial round of workgroups never
+        // appears.
         const int bpc = kernel_occupancy(*r, kind);
-        const long long target = 2LL * bpc * device_cus();
+        const long long target = 1LL * bpc * device_cus();
         long long segs = target / strips;
         if (segs < 1) segs = 1;
         int bestS = (int)((H + segs - 1) / segs);
