@@ -27,7 +27,7 @@ struct BatchPlan {
     int block = 256;
 };
 
-constexpr int kBatchRows = 64;   // default output rows per work unit
+constexpr int kBatchRows = 96;   // default output rows per work unit (64: 1% slower on the 256-image batch)
 
 int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt, BatchPlan *bp)
 {
