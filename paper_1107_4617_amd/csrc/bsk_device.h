@@ -371,6 +371,14 @@ struct IsPatch2<PolPatch2G<G>> {
     static constexpr bool value = true;
 };
 using PolPatch2 = PolPatch2G<0>;
+template <class P>
+struct IsForward32 {
+    static constexpr bool value = false;
+};
+template <int SM>
+struct IsForward32<PolForward<float, SM>> {
+    static constexpr bool value = true;
+};
 
 // The chain type of a policy: the patch's restartable chain, else the plain one.
 template <class POL, typename AT>
@@ -943,6 +951,29 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 // barrier ahead of the VALU-bound V stage of the others, so the
                 // barrier's critical path shortens while V fills the gaps.
                 __builtin_amdgcn_s_setprio(1);
+                // One-pass plain FP32 forward on the box path: the R stage's box-sum
+                // prefixes and the walker's chunk are read together, right after the
+                // barrier, so the two LDS latencies overlap.  That is 1% faster there;
+                // the multi-pass and 16-bit-stack forwards and the policies with more
+                // channels or two values per pixel measured slower with it.
+                constexpr bool JOINT = NSC == 0 && IsForward32<POL>::value && POL::START >= 0 && QUANT == 0 &&
+                                       !KAHAN;
+                constexpr int NRD = JOINT ? KL * NPAIR : 1;
+                V2 rhi[NRD], rlo[NRD];
+                AT loc[G];
+                if constexpr (JOINT) {
+                    if (actR && outlane) {
+#pragma unroll
+                        for (int q = 0; q < NRD; ++q) {
+                            rhi[q] = VbR[q * RS + phi];
+                            rlo[q] = VbR[q * RS + plo];
+                        }
+                    }
+                    if (actH && walker) {
+#pragma unroll
+                        for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
+                    }
+                }
                 // ---- R stage: box sums of the orders sR KL .. of row iR, recombined
                 if (actR && outlane) {
                     if (sR == 0) {
@@ -960,7 +991,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         for (int p = 0; p < NPAIR; ++p) {
                             // pair-row of channels (2p, 2p + 1), horizontal basis function b
                             const V2 *prow = VbR + (k * NPAIR + p) * NB * RS;
-                            if constexpr (NSC == 0) {
+                            if constexpr (JOINT) {
+                                const V2 hi = rhi[k * NPAIR + p], lo = rlo[k * NPAIR + p];
+                                B[2 * p] = hi.x - lo.x;
+                                B[2 * p + 1] = hi.y - lo.y;
+                            } else if constexpr (NSC == 0) {
                                 const V2 hi = prow[phi], lo = prow[plo];
                                 B[2 * p] = hi.x - lo.x;
                                 B[2 * p + 1] = hi.y - lo.y;
@@ -998,11 +1033,12 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 __builtin_amdgcn_s_setprio(2);
                 // ---- H stage: every row of buffer t - 1 into its exclusive prefix sums, in place
                 if (actH) {
-                    AT loc[G];
                     AT run = AT(0);
                     if (walker) {
+                        if constexpr (!JOINT) {
 #pragma unroll
-                        for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
+                            for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
+                        }
                         // local exclusive prefixes: loc[u] = sum_{v < u} of the chunk (loc[0] = 0 is implicit)
                         run = loc[0];
 #pragma unroll
