@@ -41,7 +41,7 @@ BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
 # WRITE_SIZE scaled by a 256 MiB copy (profiles/strip_kernel_fwd_rect4096_r20_s30.md).
 # Valid for this kernel build only: set to None when the kernel changes.
 HEADLINE_KERNEL = "strip_kernel<float,256,16,4,PolForward<float,0>,0,false,3>"
-HEADLINE_HBM_BYTES = None
+HEADLINE_HBM_BYTES = 283.0e6
 METRIC = "Mpixel/s + %HBM roofline, 4096\u00b2 r=20 \u03c3r=30; fwd+bwd and BF16 vs plain FP32"
 
 
