@@ -181,15 +181,15 @@ static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *oc
     constexpr int KR = kr_f32(BLOCK), KL = kl_f32(BLOCK);
     // three workgroups per compute unit where the registers allow it
     constexpr int MINB = (BLOCK == 256 && !KAHAN) ? 3 : 0;
-    if constexpr (BLOCK == 256 && !KAHAN) {
+    if constexpr (BLOCK == 256) {
         // one pass: the chain start mode as a constant (both pass sizes for the
-        // plain FP32 stack, the full pass for the 16-bit stacks)
+        // plain FP32 stack, the full pass for the 16-bit and compensated ones)
         if (a.K <= kc && (a.start_mode == 0 || a.start_mode == 1)) {
             if (kc == KR)
                 return a.start_mode == 0
-                           ? launch<float, BLOCK, KR, KL, PolForward<float, 0>, QUANT, false, MINB>(a, s, occ)
-                           : launch<float, BLOCK, KR, KL, PolForward<float, 1>, QUANT, false, MINB>(a, s, occ);
-            if constexpr (QUANT == 0)
+                           ? launch<float, BLOCK, KR, KL, PolForward<float, 0>, QUANT, KAHAN, MINB>(a, s, occ)
+                           : launch<float, BLOCK, KR, KL, PolForward<float, 1>, QUANT, KAHAN, MINB>(a, s, occ);
+            if constexpr (QUANT == 0 && !KAHAN)
                 return a.start_mode == 0
                            ? launch<float, BLOCK, KR / 2, KL, PolForward<float, 0>, 0, false, MINB>(a, s, occ)
                            : launch<float, BLOCK, KR / 2, KL, PolForward<float, 1>, 0, false, MINB>(a, s, occ);
