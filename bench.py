@@ -102,10 +102,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--kernel-only", nargs="?", const="headline", default=None,
-                    choices=["headline", "spatial", "poly", "poly_trunc", "nlm2"],
-                    help="profiling mode: run the headline forward (or the spatial-kernel or polynomial-"
-                         "kernel forward at the same size) --steps times after --warmup, and a device copy "
-                         "of --copy-mib MiB; print nothing but a summary line")
+                    choices=["headline", "spatial", "poly", "poly_trunc", "nlm2", "fp64", "fwd_bwd"],
+                    help="profiling mode: run the headline forward (or the spatial-kernel, polynomial-"
+                         "kernel, patch, FP64 or training forward + adjoint form at the same size) --steps "
+                         "times after --warmup, and a device copy of --copy-mib MiB; print nothing but a "
+                         "summary line")
     ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -150,6 +151,16 @@ def main():
             fwd = fwd_poly
         elif args.kernel_only == "poly_trunc":
             fwd = fwd_poly_t
+        elif args.kernel_only == "fp64":
+            img64 = img.double()
+            out64 = torch.empty_like(img64)
+            fwd = lambda: bilateral(img64, radius, sigma, T, N=N, precision="fp64", out=out64)  # noqa: E731
+        elif args.kernel_only == "fwd_bwd":
+            g = torch.randn(img.shape, generator=torch.Generator().manual_seed(5)).to(dev)
+
+            def fwd():
+                o, sv = bilateral_train(img, radius, sigma, T, N)
+                bilateral_backward(img, g, radius, sigma, T, N, out=o, saved=sv)
         # a plain device copy of known size: reference for the HBM byte counters
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, device=dev)
