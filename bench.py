@@ -102,11 +102,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--kernel-only", nargs="?", const="headline", default=None,
-                    choices=["headline", "spatial", "poly", "poly_trunc", "nlm2", "fp64", "fwd_bwd"],
+                    choices=["headline", "spatial", "poly", "poly_trunc", "nlm2", "fp64", "fwd_bwd", "bf16",
+                             "batched"],
                     help="profiling mode: run the headline forward (or the spatial-kernel, polynomial-"
-                         "kernel, patch, FP64 or training forward + adjoint form at the same size) --steps "
-                         "times after --warmup, and a device copy of --copy-mib MiB; print nothing but a "
-                         "summary line")
+                         "kernel, patch, FP64, training forward + adjoint or 16-bit form at the same size, "
+                         "or the 256-image batch) --steps times after --warmup, and a device copy of "
+                         "--copy-mib MiB; print nothing but a summary line")
     ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -161,6 +162,15 @@ def main():
             def fwd():
                 o, sv = bilateral_train(img, radius, sigma, T, N)
                 bilateral_backward(img, g, radius, sigma, T, N, out=o, saved=sv)
+        elif args.kernel_only == "bf16":
+            fwd = lambda: bilateral(img, radius, sigma, T, N=N, precision="bf16", weight_eps=1e-7,  # noqa: E731
+                                    out=out)
+        elif args.kernel_only == "batched":
+            specs = wl.batch_specs(256, seed=4)
+            imgs = [torch.from_numpy(wl.gradient_image(h, w, s)).to(dev) for (h, w, r, sg, s) in specs]
+            outs = [torch.empty_like(x) for x in imgs]
+            radii, sigs = [s[2] for s in specs], [s[3] for s in specs]
+            fwd = lambda: bilateral_batched(imgs, radii, sigs, T, outs=outs)  # noqa: E731
         # a plain device copy of known size: reference for the HBM byte counters
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, device=dev)
