@@ -103,9 +103,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--kernel-only", nargs="?", const="headline", default=None,
                     choices=["headline", "spatial", "poly", "poly_trunc", "nlm2", "fp64", "fwd_bwd", "bf16",
-                             "batched"],
+                             "batched", "alg1"],
                     help="profiling mode: run the headline forward (or the spatial-kernel, polynomial-"
-                         "kernel, patch, FP64, training forward + adjoint or 16-bit form at the same size, "
+                         "kernel, patch, FP64, training forward + adjoint, 16-bit or Algorithm 1 form at the same "
+                         "size, "
                          "or the 256-image batch) --steps times after --warmup, and a device copy of "
                          "--copy-mib MiB; print nothing but a summary line")
     ap.add_argument("--copy-mib", type=int, default=256)
@@ -162,6 +163,9 @@ def main():
             def fwd():
                 o, sv = bilateral_train(img, radius, sigma, T, N)
                 bilateral_backward(img, g, radius, sigma, T, N, out=o, saved=sv)
+        elif args.kernel_only == "alg1":
+            # Algorithm 1: the q_2 Gaussian-like spatial filter alone, over the same window
+            fwd = lambda: spatial_filter(img, radius, sig_s, 2, out=out)  # noqa: E731
         elif args.kernel_only == "bf16":
             fwd = lambda: bilateral(img, radius, sigma, T, N=N, precision="bf16", weight_eps=1e-7,  # noqa: E731
                                     out=out)
