@@ -108,24 +108,47 @@ double oracle_kernel_deriv(double t, double sigma_r, int N)
     return -(double)N * ipow(cos(a), N - 1) * sin(a) / s;
 }
 
-/* Binomial weight w_n = 2^-N C(N, n) through the log-gamma function. */
-static double binom_weight(int N, int n)
+/* Binomial weights w_n = 2^-N C(N, n), n = 0..N, into w[0..N].
+ * Section 3.1 discards the basis functions whose weight falls below a
+ * threshold, so deciding w_n < eps at an eps equal to a kept weight needs each
+ * weight as the double nearest its exact value.  For N <= 130 the binomial
+ * coefficients come from Pascal's triangle in unsigned 128-bit integers
+ * (C(130, 65) < 2^127, so every entry is exact); the conversion to double
+ * rounds once to nearest and the scaling by 2^-N is exact.  Beyond N = 130 the
+ * log-gamma form is used, which is accurate to about 1e-13 relative. */
+#define ORACLE_EXACT_BINOM_MAX 130
+static void binom_row(int N, double *w)
 {
-    double lw = lgamma((double)N + 1.0) - lgamma((double)n + 1.0)
-              - lgamma((double)(N - n) + 1.0) - (double)N * log(2.0);
-    return exp(lw);
+    if (N <= ORACLE_EXACT_BINOM_MAX) {
+        unsigned __int128 c[ORACLE_EXACT_BINOM_MAX + 1];
+        c[0] = 1;
+        for (int row = 1; row <= N; ++row) {
+            c[row] = 1;
+            for (int n = row - 1; n >= 1; --n) c[n] += c[n - 1];
+        }
+        for (int n = 0; n <= N; ++n) w[n] = ldexp((double)c[n], -N);
+        return;
+    }
+    for (int n = 0; n <= N; ++n) {
+        double lw = lgamma((double)N + 1.0) - lgamma((double)n + 1.0)
+                  - lgamma((double)(N - n) + 1.0) - (double)N * log(2.0);
+        w[n] = exp(lw);
+    }
 }
 
-/* Number of terms with w_n >= eps, and the dropped mass sum_{w_n < eps} w_n. */
+/* Number of terms kept (w_n >= eps: a weight is dropped only when strictly
+ * below eps), and the dropped mass sum_{w_n < eps} w_n. */
 int oracle_trunc_terms(int N, double eps, double *dropped)
 {
+    double *w = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+    binom_row(N, w);
     int kept = 0;
     double drop = 0.0;
     for (int n = 0; n <= N; ++n) {
-        double w = binom_weight(N, n);
-        if (w >= eps) kept++;
-        else drop += w;
+        if (w[n] >= eps) kept++;
+        else drop += w[n];
     }
+    free(w);
     if (dropped) *dropped = drop;
     return kept;
 }
@@ -134,12 +157,13 @@ int oracle_trunc_terms(int N, double eps, double *dropped)
 double oracle_trunc_kernel(double t, double sigma_r, int N, double eps)
 {
     if (N == 0) return 1.0;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+    binom_row(N, w);
     double s = sigma_r * sqrt((double)N);
     double acc = 0.0;
-    for (int n = 0; n <= N; ++n) {
-        double w = binom_weight(N, n);
-        if (w >= eps) acc += w * cos((double)(2 * n - N) * t / s);
-    }
+    for (int n = 0; n <= N; ++n)
+        if (w[n] >= eps) acc += w[n] * cos((double)(2 * n - N) * t / s);
+    free(w);
     return acc;
 }
 
@@ -184,14 +208,17 @@ static void kern_init(kern_t *k, double sigma_r, int N, double eps, int truncate
         k->w = (double *)malloc(sizeof(double) * (size_t)(N + 1));
         k->om = (double *)malloc(sizeof(double) * (size_t)(N + 1));
         double s = sigma_r * sqrt((double)N);
+        double *wr = (double *)malloc(sizeof(double) * (size_t)(N + 1));
+        binom_row(N, wr);
         for (int n = 0; n <= N; ++n) {
-            double w = binom_weight(N, n);
+            double w = wr[n];
             if (w >= eps) {
                 k->w[k->nterm] = w;
                 k->om[k->nterm] = (double)(2 * n - N) / s;
                 k->nterm++;
             }
         }
+        free(wr);
     }
 }
 

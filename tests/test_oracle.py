@@ -325,6 +325,80 @@ def test_truncated_filter_reduces_to_exact_when_nothing_dropped(oracle):
     assert np.max(np.abs(a - b)) < 1e-11
 
 
+def _brute_truncated(f, r, sigma, N, eps, pixels):
+    """The truncated filter by brute force, independent of the oracle: the kernel of
+    Section 3.1 after discarding every unfolded basis function whose exact weight
+    w_n = C(N, n) / 2^N is strictly below eps (the comparison in exact rationals),
+    summed per window element with math.fsum."""
+    H, W = f.shape
+    s = sigma * math.sqrt(N)
+    eps_q = Fraction(eps)
+    kept = [(math.comb(N, n) / 2 ** N, (2 * n - N) / s) for n in range(N + 1)
+            if Fraction(math.comb(N, n), 2 ** N) >= eps_q]
+    out = []
+    for (i, j) in pixels:
+        fx = float(f[i, j])
+        ps, qs = [], []
+        for y in range(max(0, i - r), min(H - 1, i + r) + 1):
+            for x in range(max(0, j - r), min(W - 1, j + r) + 1):
+                fy = float(f[y, x])
+                k = math.fsum(w * math.cos(om * (fy - fx)) for w, om in kept)
+                ps.append(k * fy)
+                qs.append(k)
+        out.append(math.fsum(ps) / math.fsum(qs))
+    return np.array(out), len(kept)
+
+
+def _eps_cases(N):
+    """Thresholds for N: the precision form's 1e-7; one equal to a kept weight (exactly
+    representable for N <= 50, so only a strict drop keeps it); and one at 1.5 times a
+    weight, which the unfolded rule drops but a rule on the folded weights 2 w_n keeps."""
+    w = [Fraction(math.comb(N, n), 2 ** N) for n in range(N + 1)]
+    k = next(n for n in range(N + 1) if w[n] >= Fraction(1, 10 ** 4))   # a mid-sized weight
+    cases = [1e-7, 1.5 * float(w[k - 1])]
+    if N <= 50:
+        assert Fraction(float(w[k])) == w[k]
+        cases.append(float(w[k]))
+    return cases
+
+
+@pytest.mark.parametrize("N", [30, 117])
+def test_truncated_filter_matches_brute_force(oracle, N):
+    """Pins the oracle's truncated filter (Section 3.1, less significant basis functions
+    discarded) at eps > 0: whole-image and per-pixel entry points against a brute force
+    with exact binomial weights and the strict drop w_n < eps, on a non-square image with
+    a window that reaches every border."""
+    f = wl.rect_image(9, 11, seed=17, n_rect=4)
+    sigma, r = (30.0, 3) if N == 30 else (15.0, 2)
+    pixels = [(i, j) for i in range(9) for j in range(11)]
+    idx = np.array([i * 11 + j for i, j in pixels], dtype=np.int64)
+    for eps in _eps_cases(N):
+        ref, nkept = _brute_truncated(f, r, sigma, N, eps, pixels)
+        kept, _ = oracle.trunc_terms(N, eps)
+        assert kept == nkept, (N, eps)
+        full = oracle.bilateral(f, r, sigma, N, eps=eps, truncated=True).ravel()
+        at = oracle.bilateral_at(f, idx, r, sigma, N, eps=eps, truncated=True)
+        assert np.max(np.abs(full - ref)) <= 1e-11 * T, (N, eps)
+        assert np.max(np.abs(at - ref)) <= 1e-11 * T, (N, eps)
+
+
+def test_truncation_threshold_is_strict_and_unfolded(oracle):
+    """At eps equal to a kept weight that weight stays (drop only w_n < eps); at 1.5 times
+    a weight that weight goes although its folded pair weight 2 w_n exceeds eps."""
+    N = 30
+    w = [math.comb(N, n) / 2 ** N for n in range(N + 1)]
+    k = 9
+    assert oracle.trunc_terms(N, w[k])[0] == sum(1 for x in w if x >= w[k]) == N + 1 - 2 * k
+    assert oracle.trunc_terms(N, 1.5 * w[k])[0] == N + 1 - 2 * (k + 1)
+    sigma = 30.0
+    s = sigma * math.sqrt(N)
+    for t in (0.0, 13.0, 77.0, 200.0):
+        exact_keep = math.fsum(w[n] * math.cos((2 * n - N) * t / s) for n in range(k, N + 1 - k))
+        assert abs(oracle.trunc_kernel(t, sigma, N, w[k]) - exact_keep) <= 1e-15
+        drop_k = math.fsum(w[n] * math.cos((2 * n - N) * t / s) for n in range(k + 1, N - k))
+        assert abs(oracle.trunc_kernel(t, sigma, N, 1.5 * w[k]) - drop_k) <= 1e-15
+
+
 def test_sampled_matches_full(oracle):
     f = wl.rect_image(40, 50, seed=2)
     full, P, Q = oracle.bilateral(f, 6, 30.0, 30, return_pq=True)
