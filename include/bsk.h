@@ -221,7 +221,10 @@ typedef struct {
 
 /*
  * Filter B independent images of different sizes, radii and sigma_r in ONE
- * persistent kernel launch.  descs is a HOST array of B descriptors.  Work
+ * persistent kernel launch.  Each image is filtered exactly as by
+ * bilateral_shiftable_ex (eq. (3) through Algorithm 2, box spatial kernel,
+ * raised-cosine range kernel of eq. (6) at its own order); gathering many
+ * images into one launch has no counterpart in the paper.  descs is a HOST array of B descriptors.  Work
  * units (image, strip, row segment) are claimed from a device work counter;
  * the launch shape comes from the autotuner (bsk_autotune) when tuned.
  * The descriptor table is staged through a library-owned device buffer, so
@@ -242,11 +245,24 @@ int bilateral_shiftable_batched_graph(const bsk_image_desc *descs, int B, float 
 /* N_0 = ceil((2T / (pi sigma_r))^2) (Section 3.1); -1 on invalid input. */
 int bsk_order_for(float sigma_r, float T);
 
-/* Folded plan of order N with truncation eps: number of folded orders K and
- * the dropped unfolded weight mass (both may be NULL). */
+/* Plan of the raised-cosine kernel of order N (Section 3): the binomial
+ * theorem expands cos^N into the N+1 terms w_n cos((2n - N) t / (sigma_r sqrt N)),
+ * w_n = 2^-N C(N, n); terms n and N - n have equal weights and opposite
+ * frequencies and fold into one order (K_full = floor(N/2) + 1 orders).
+ * Section 3.1 (its closing paragraph) discards the less significant basis
+ * functions: with eps > 0 every unfolded term whose weight is strictly below
+ * eps is dropped.
+ *   N:       order, 0 .. 1000000
+ *   eps:     threshold, finite and >= 0 (0 keeps every term)
+ *   K:       (nullable) receives the folded orders kept
+ *   dropped: (nullable) receives the dropped unfolded mass sum_{w_n < eps} w_n,
+ *            which bounds |phi - phi_eps| everywhere
+ * Host only (no device call).  Returns BSK_OK or BSK_EINVAL. */
 int bsk_plan_info(int N, double eps, int *K, double *dropped);
 
-/* Dropped unfolded weight mass sum_{w_n < eps} w_n (0 if nothing dropped). */
+/* The dropped mass of bsk_plan_info, sum_{w_n < eps} w_n (Section 3.1's
+ * discarded basis functions; 0 if nothing is dropped), or -1.0 for invalid
+ * N or eps.  Host only. */
 double bsk_truncation_error(int N, double eps);
 
 /* N_p = ceil(T^2 / (2 sigma_r^2)) for the polynomial range kernel; -1 on
@@ -276,6 +292,17 @@ int bsk_poly_plan_info(int N, float sigma_r, float T, double eps, int *coefs, do
 int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float T, void *out,
                  const bsk_options *opt, const char *path, void *stream, int *best_block,
                  int *best_rows, int *best_chunk, double *best_ms);
+
+/*
+ * Caps the device memory the library holds as per-stream workspace (the
+ * multi-pass accumulator planes, tables and partial sums that the entry
+ * points above allocate on first use and keep), per device, in bytes; 0 (the
+ * default) removes the cap.  A call whose workspace would exceed the cap
+ * fails with BSK_ENOMEM before anything is queued.  Buffers already held are
+ * kept (bsk_release() frees them); HIP graphs of the batched entry point own
+ * their buffers outside this cap.  Host only; BSK_EINVAL if bytes < 0.
+ */
+int bsk_set_workspace_limit(long long bytes);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *bsk_last_error(void);

@@ -4,11 +4,13 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsk.so")
-SOURCES = ["bsk_kernels.hip", "bsk_batched.hip", "bsk_poly.hip", "bsk_plan.cpp", "bsk_api.cpp", "bsk_batched.cpp"]
+SOURCES = ["bsk_kernels.hip", "bsk_batched.hip", "bsk_poly.hip", "bsk_plan.cpp", "bsk_api.cpp",
+           "bsk_batched.cpp"]
 
 # Packed FP32 instructions are turned off in the device code; hipcc's host
 # pass warns that it does not know this feature, which is harmless.
@@ -17,20 +19,26 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def _compile(src: str, verbose: bool) -> str:
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(HERE, "_build", src + ".o")
+    cmd = ["hipcc", *HIPFLAGS, "-c", path, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source (in parallel, at most `jobs` at once; 0 = one per source
+    up to the CPU count) and links libbsk.so."""
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(HERE, "_build", src + ".o")
-        cmd = ["hipcc", *HIPFLAGS, "-c", path, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
-        objs.append(obj)
+    n = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

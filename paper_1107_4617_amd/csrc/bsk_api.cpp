@@ -48,18 +48,34 @@ struct WsKey {
 struct WsBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    unsigned long long gen = 0;
 };
 std::mutex g_ws_mu;
 std::map<WsKey, WsBuf> g_ws;
+unsigned long long g_ws_gen = 0;
+long long g_ws_limit = 0;   // bytes of library workspace per device; 0 = unlimited
 
-int get_ws(void *stream, int slot, size_t bytes, void **out)
+int get_ws(void *stream, int slot, size_t bytes, void **out, unsigned long long *gen)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        if (g_ws_limit > 0 && bytes > (size_t)g_ws_limit)
+            return fail(BSK_ENOMEM, "workspace of %zu bytes exceeds the limit of %lld bytes", bytes, g_ws_limit);
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_ws_mu);
     WsBuf &b = g_ws[WsKey{dev, stream, slot}];
     if (b.bytes < bytes) {
+        if (g_ws_limit > 0) {
+            size_t held = 0;
+            for (auto &kv : g_ws)
+                if (kv.first.dev == dev) held += kv.second.bytes;
+            if (held - b.bytes + bytes > (size_t)g_ws_limit)
+                return fail(BSK_ENOMEM, "workspace of %zu bytes would exceed the limit of %lld bytes "
+                            "(%zu held on the device)", bytes, g_ws_limit, held);
+        }
         if (b.ptr) {
             // the previous buffer may still be read by queued work on this stream
             e = hipStreamSynchronize((hipStream_t)stream);
@@ -75,8 +91,10 @@ int get_ws(void *stream, int slot, size_t bytes, void **out)
             return fail(BSK_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
         }
         b.bytes = bytes;
+        b.gen = ++g_ws_gen;
     }
     *out = b.ptr;
+    if (gen) *gen = b.gen;
     return BSK_OK;
 }
 
@@ -434,7 +452,7 @@ struct PolyUpload {
     std::shared_ptr<const bsk::PolyPlan> keep;   // keeps the plan (and so the key) alive
     int np = 0;
     int prec = -1;
-    void *ptr = nullptr;
+    unsigned long long gen = 0;   // workspace generation the table was uploaded into
     std::vector<unsigned char> host;
 };
 std::mutex g_poly_mu;
@@ -450,7 +468,8 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
     const size_t nrows = (size_t)(2 * std::max(pp.N, np) + 3) * bsk::kPolyRow;
     const size_t nsig = (size_t)(2 * np + 2);
     void *tab = nullptr;
-    int st = get_ws(stream, 6, (nrows + nsig) * esz, &tab);
+    unsigned long long gen = 0;
+    int st = get_ws(stream, kWsPolyTab, (nrows + nsig) * esz, &tab, &gen);
     if (st) return st;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -458,7 +477,7 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
     {
         std::lock_guard<std::mutex> lk(g_poly_mu);
         PolyUpload &u = g_poly_up[std::make_pair(dev, stream)];
-        if (u.plan != &pp || u.np != np || u.prec != r.prec || u.ptr != tab) {
+        if (u.plan != &pp || u.np != np || u.prec != r.prec || u.gen != gen) {
             if (!u.host.empty()) {
                 // an earlier upload from the host copy may still be pending on the stream
                 e = hipStreamSynchronize((hipStream_t)stream);
@@ -481,7 +500,7 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
             u.keep = r.poly;
             u.np = np;
             u.prec = r.prec;
-            u.ptr = tab;
+            u.gen = gen;
         }
     }
     bsk::PolyArgs a;
@@ -503,7 +522,7 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
     a.sig = (const char *)tab + nrows * esz;
     if (np > kc) {
         void *ws = nullptr;
-        st = get_ws(stream, 0, 6 * (size_t)H * W * esz, &ws);
+        st = get_ws(stream, kWsAcc, 6 * (size_t)H * W * esz, &ws);
         if (st) return st;
         a.ws = ws;
     }
@@ -517,7 +536,7 @@ int poly_forward(const void *img, int H, int W, const Resolved &r, void *out, vo
 // workspace slot of the stream when their contents or the buffer change.
 struct TabUpload {
     std::vector<unsigned char> host;
-    void *ptr = nullptr;
+    unsigned long long gen = 0;   // workspace generation the table was uploaded into
 };
 std::mutex g_tab_mu;
 std::map<std::tuple<int, void *, int>, TabUpload> g_tab_up;
@@ -525,14 +544,15 @@ std::map<std::tuple<int, void *, int>, TabUpload> g_tab_up;
 int upload_table(void *stream, int slot, const std::vector<unsigned char> &bytes, void **out)
 {
     void *dst = nullptr;
-    int st = get_ws(stream, slot, bytes.size(), &dst);
+    unsigned long long gen = 0;
+    int st = get_ws(stream, slot, bytes.size(), &dst, &gen);
     if (st) return st;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_tab_mu);
     TabUpload &u = g_tab_up[std::make_tuple(dev, stream, slot)];
-    if (u.ptr != dst || u.host != bytes) {
+    if (u.gen != gen || u.host != bytes) {
         if (!u.host.empty()) {
             // an earlier upload from the host copy may still be pending on the stream
             e = hipStreamSynchronize((hipStream_t)stream);
@@ -541,7 +561,7 @@ int upload_table(void *stream, int slot, const std::vector<unsigned char> &bytes
         u.host = bytes;
         e = hipMemcpyAsync(dst, u.host.data(), u.host.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "table upload");
-        u.ptr = dst;
+        u.gen = gen;
     }
     *out = dst;
     return BSK_OK;
@@ -630,7 +650,7 @@ int nlm2_impl(const float *img, int H, int W, int radius, float sigma_1, float s
         for (int m = 0; m < K2; ++m) vf[base + m] = (float)(w1[g] * p2.v[m]);
     }
     void *dtab = nullptr;
-    st = upload_table(stream, 7, tab, &dtab);
+    st = upload_table(stream, kWsPatchTab, tab, &dtab);
     if (st) return st;
 
     bsk::StripArgs a;
@@ -659,7 +679,7 @@ int nlm2_impl(const float *img, int H, int W, int radius, float sigma_1, float s
     a.vf_dev = (const float *)dtab;
     if (K > kc) {
         void *ws = nullptr;
-        st = get_ws(stream, 0, (size_t)bsk::acc_count_forward() * H * W * 4, &ws);
+        st = get_ws(stream, kWsAcc, (size_t)bsk::acc_count_forward() * H * W * 4, &ws);
         if (st) return st;
         a.ws = ws;
     }
@@ -686,7 +706,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
     a.io.out = out;
     if (r.plan.K > kc) {
         void *ws = nullptr;
-        st = get_ws(stream, 0, (size_t)bsk::acc_count_forward() * H * W * esz, &ws);
+        st = get_ws(stream, kWsAcc, (size_t)bsk::acc_count_forward() * H * W * esz, &ws);
         if (st) return st;
         a.ws = ws;
     }
@@ -694,7 +714,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
         // phase tables (cos, sin)(nu_j y) for the rows and columns, then the kernel
         void *tab = nullptr;
         const size_t nrow = (size_t)H * r.sp.nsc * 2, ncol = (size_t)W * r.sp.nsc * 2;
-        st = get_ws(stream, 5, (nrow + ncol) * sizeof(float), &tab);
+        st = get_ws(stream, kWsPhase, (nrow + ncol) * sizeof(float), &tab);
         if (st) return st;
         float *rowtab = (float *)tab, *coltab = rowtab + nrow;
         hipError_t e = bsk::launch_phase_table(r.sp, H, rowtab, (hipStream_t)stream);
@@ -724,7 +744,7 @@ int train_impl(const float *img, int H, int W, const Resolved &r, float *out, fl
     a.io.out2 = saved;
     if (r.plan.K > r.kc) {
         void *ws = nullptr;
-        int st = get_ws(stream, 1, (size_t)bsk::acc_count_train() * H * W * 4, &ws);
+        int st = get_ws(stream, kWsTrainAcc, (size_t)bsk::acc_count_train() * H * W * 4, &ws);
         if (st) return st;
         a.ws = ws;
     }
@@ -792,7 +812,7 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
 
     if (!out) {
         void *tmp = nullptr;
-        st = get_ws(stream, 2, 4 * n, &tmp);
+        st = get_ws(stream, kWsBwdTrain, 4 * n, &tmp);
         if (st) return st;
         float *u = (float *)tmp;
         float *sv = u + (size_t)H * W;
@@ -816,12 +836,12 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
     a.io.out = grad_img;
     const int nred = nblocks(r, H, W);
     void *red = nullptr;
-    st = get_ws(stream, 3, (size_t)nred * sizeof(double), &red);
+    st = get_ws(stream, kWsBwdRed, (size_t)nred * sizeof(double), &red);
     if (st) return st;
     a.red = (double *)red;
     if (r.plan.K > r.kc) {
         void *ws = nullptr;
-        st = get_ws(stream, 4, (size_t)bsk::acc_count_backward() * H * W * 4, &ws);
+        st = get_ws(stream, kWsBwdAcc, (size_t)bsk::acc_count_backward() * H * W * 4, &ws);
         if (st) return st;
         a.ws = ws;
     }
@@ -881,6 +901,14 @@ int bsk_poly_plan_info(int N, float sigma_r, float T, double eps, int *coefs, do
 }
 
 const char *bsk_last_error(void) { return g_err; }
+
+int bsk_set_workspace_limit(long long bytes)
+{
+    if (bytes < 0) return fail(BSK_EINVAL, "workspace limit must be >= 0");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_ws_limit = bytes;
+    return BSK_OK;
+}
 
 void bsk_release_batched(void);
 

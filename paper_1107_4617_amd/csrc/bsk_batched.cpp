@@ -350,14 +350,14 @@ int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T, con
     std::vector<char> host;
     pack_tables(bp, &host, &off_v, &off_f, &off_c);
     DeviceBatch db;
-    st = get_ws(stream, 5, host.size(), &db.tab);
-    if (st) return st;
     if (bp.ws_elems > 0) {
         void *w = nullptr;
-        st = get_ws(stream, 6, (size_t)bp.ws_elems * sizeof(float), &w);
+        st = get_ws(stream, kWsBatchAcc, (size_t)bp.ws_elems * sizeof(float), &w);
         if (st) return st;
         db.ws = (float *)w;
     }
+    st = get_ws(stream, kWsBatchTab, host.size(), &db.tab);
+    if (st) return st;
     set_args(&db, bp, off_v, off_f, off_c);
     st = stage_upload(stream, host, db.tab);
     if (st) return st;

@@ -1169,6 +1169,16 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         for (int q = 0; q < NACC; ++q) acc[q] += ((AT *)gm.ws)[q * plane + o];
                     }
                     if (last) {
+                        if constexpr (QUANT != 0 && IsForward32<POL>::value) {
+                            // 16-bit stacks: the exact normaliser is at least the kernel's
+                            // centre value (about 1) for a non-negative kernel; one that fell
+                            // below 1/2 is dominated by quantisation error, and the pixel
+                            // keeps its own value instead of an unbounded ratio
+                            if (!(acc[0] >= AT(0.5))) {
+                                acc[0] = AT(1);
+                                acc[1] = auxc[0];
+                            }
+                        }
                         POL::template finalize<AT>(a, iR, jx, ref, auxc, acc, &red);
                     } else {
 #pragma unroll

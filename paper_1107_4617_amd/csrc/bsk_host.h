@@ -11,8 +11,27 @@ namespace host {
 
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
-// Grow-only device buffer per (device, stream, slot).
-int get_ws(void *stream, int slot, size_t bytes, void **out);
+// Workspace slots, one per kind of use, so a buffer whose contents are cached
+// across calls (the polynomial kernel's coefficient table, the patch filter's
+// weights) is never written by another kind of call.
+enum WsSlot {
+    kWsAcc = 0,        // multi-pass accumulators: forward, patch, polynomial (rewritten by every call)
+    kWsTrainAcc = 1,   // training-forward multi-pass accumulators
+    kWsBwdTrain = 2,   // out and saved planes when the adjoint recomputes the training forward
+    kWsBwdRed = 3,     // per-workgroup partial sums of the sigma_r gradient
+    kWsBwdAcc = 4,     // adjoint multi-pass accumulators
+    kWsPhase = 5,      // spatial-kernel phase tables (rewritten by every call)
+    kWsPolyTab = 6,    // polynomial-kernel coefficient tables (cached)
+    kWsPatchTab = 7,   // two-pixel-patch weight table (cached)
+    kWsBatchTab = 8,   // batched descriptor and weight tables (uploaded by every call)
+    kWsBatchAcc = 9    // batched multi-pass accumulators
+};
+// Grow-only device buffer per (device, stream, slot).  *gen (nullable)
+// receives the buffer's allocation generation, unique across the process, so
+// a cache keyed on it notices a reallocation even at the same address.
+// Requests beyond the workspace limit (bsk_set_workspace_limit) fail with
+// BSK_ENOMEM.
+int get_ws(void *stream, int slot, size_t bytes, void **out, unsigned long long *gen = nullptr);
 int device_cus();
 bool finite_pos(double x);
 

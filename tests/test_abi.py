@@ -159,6 +159,34 @@ def test_batched_validation(lib):
     assert lib.bilateral_shiftable_batched_graph(d, 2, 255.0, ctypes.byref(o), 7, None) == -1  # default stream
 
 
+def test_workspace_limit_reports_enomem(lib):
+    """A multi-pass request (N = 117: 59 folded orders, several passes) keeps two planes of
+    partial accumulators in a library workspace.  Under a workspace cap smaller than that
+    the call fails with BSK_ENOMEM before anything is queued (so fake device pointers are
+    never touched), and lifting the cap restores the default."""
+    big, big2 = 1 << 40, 1 << 41
+    o = _lib.Options()
+    o.order_mode, o.N = 1, 117
+    try:
+        assert lib.bsk_set_workspace_limit(1 << 20) == _lib.BSK_OK
+        assert _call_ex(lib, img=big, out=big2, H=1024, W=1024, r=5, s=15.0, opt=o) == _lib.BSK_ENOMEM
+        assert b"limit" in lib.bsk_last_error()
+        # the training forward (five planes) and the batched path are capped alike
+        o32 = _lib.Options()
+        o32.order_mode, o32.N = 1, 117
+        out = ctypes.c_void_p(big2)
+        saved = ctypes.c_void_p(big2 + (1 << 32))
+        assert lib.bilateral_shiftable_train(ctypes.c_void_p(big), 1024, 1024, 5, 15.0, 255.0,
+                                             ctypes.byref(o32), out, saved, None) == _lib.BSK_ENOMEM
+        d = (_lib.ImageDesc * 1)()
+        d[0].img, d[0].out = big, big2
+        d[0].H, d[0].W, d[0].radius, d[0].sigma_r, d[0].N = 1024, 1024, 5, 15.0, 117
+        assert lib.bilateral_shiftable_batched(d, 1, 255.0, ctypes.byref(_lib.Options()), None) == _lib.BSK_ENOMEM
+        assert lib.bsk_set_workspace_limit(-1) == _lib.BSK_EINVAL
+    finally:
+        assert lib.bsk_set_workspace_limit(0) == _lib.BSK_OK
+
+
 def _no_device():
     import torch
     return torch.cuda.device_count() == 0

@@ -32,9 +32,10 @@ def test_batched_equals_single_image_path_and_oracle():
         # same launch shape (256 lanes, 96-row units, the pass size both paths choose
         # for the image's order count); the single-image path compiles a one-pass
         # launch with its chain start mode as a constant, which may round differently
+        # (bound: about 30 FP32 rounding units of values up to 255)
         single = bilateral(x, r, sg, T, block=256, strip_h=96)
         torch.cuda.synchronize()
-        assert float((single - y).abs().max()) <= 1e-4 * T
+        assert float((single - y).abs().max()) <= 5e-4
     for b in (0, 5, 13):
         H, W, r, sg, _ = specs[b]
         ref = oracle.bilateral(imgs[b].cpu().numpy(), r, sg, order_for(sg, T))
@@ -72,7 +73,7 @@ def test_full_batch_256_images():
         H, W, r, sg, _ = specs[b]
         single = bilateral(imgs[b], r, sg, T, block=256, strip_h=96)
         torch.cuda.synchronize()
-        assert float((single - outs[b]).abs().max()) <= 1e-4 * T
+        assert float((single - outs[b]).abs().max()) <= 5e-4
         f = imgs[b].cpu().numpy()
         idx = rng.integers(0, H * W, 400)
         ref = oracle.bilateral_at(f, idx, r, sg, order_for(sg, T))

@@ -192,23 +192,84 @@ def test_rect4096_r20_sampled():
     assert np.max(err) <= TOL32, np.max(err)
 
 
-@pytest.mark.parametrize("kahan", [False, True])
-def test_precision_forms_rect4096_full_image(rect4096, kahan):
+# Which 16-bit stacks meet 2e-3 T at their worst pixels.  A 16-bit stack perturbs the kernel by
+# about one rounding unit u per order, so the output moves by roughly u sqrt(|B|) |f_y - out| / Q:
+# it is largest where few neighbours resemble the pixel and the normaliser Q is small.  The
+# Q15 stack (u = 2^-15 on [-1, 1]) meets the tolerance at the headline workload; the float16
+# (u = 2^-11 relative) and bfloat16 (2^-8) stacks do not, and at 8192^2, r = 32, sigma_r = 15
+# (|B| = 4225, normalisers down to ~1) none does.  The failing forms are strict xfails: the
+# day one of them passes, the test says so.
+PRECISION_FORMS = [(p, k) for p in ("i16", "fp16", "bf16") for k in (False, True)]
+MEETS_4096 = {("i16", False): True, ("i16", True): True, ("fp16", False): False, ("fp16", True): False,
+              ("bf16", False): False, ("bf16", True): False}
+MEETS_8192 = {key: False for key in PRECISION_FORMS}
+
+
+def _worst(err, n):
+    """Flat indices of the n largest entries of err."""
+    flat = err.ravel()
+    return np.argpartition(flat, -n)[-n:]
+
+
+def _form_param(prec, kahan, meets):
+    marks = [] if meets[(prec, kahan)] else [pytest.mark.xfail(
+        strict=True, reason=f"{prec} stack{' + Kahan' if kahan else ''}: max error above 2e-3 T where the "
+                            "normaliser is small (quantisation of the stack, not the sums)")]
+    return pytest.param(prec, kahan, marks=marks, id=f"{prec}{'-kahan' if kahan else ''}")
+
+
+@pytest.mark.parametrize("prec,kahan", [_form_param(p, k, MEETS_4096) for p, k in PRECISION_FORMS])
+def test_precision_form_rect4096_worst_pixels(rect4096, prec, kahan):
     """Headline workload (4096^2, r=20, sigma_r=30, N=30) with the stack held in 16 bits and
-    weights below 1e-7 dropped (14 of 16 folded orders), with and without compensated
-    vertical sums: every pixel against the exact oracle, sampled pixels against the
-    oracle's truncated kernel.  The 16-bit fixed-point stack stays within 2e-3 T
-    everywhere; bfloat16 and float16 stacks do not (their error is largest where the
-    normaliser is small) and are held to looser regression bounds; the measured errors
-    are recorded in the design notes."""
+    weights below 1e-7 dropped (14 of 16 folded orders): every pixel against the exact oracle,
+    and the 2000 pixels where the form departs most from the FP32 path plus 800 random ones
+    against the oracle's truncated kernel, all at 2e-3 T."""
     f, ref = rect4096
-    idx = _sample_idx(4096, 4096, 800, 44)
+    out32 = _gpu_filter(f, 20, 30.0, N=30)
+    out = _gpu_filter(f, 20, 30.0, N=30, precision=prec, weight_eps=1e-7, kahan=kahan)
+    err_exact = float(np.max(np.abs(out - ref)))
+    idx = np.union1d(_worst(np.abs(out - out32), 2000), _sample_idx(4096, 4096, 800, 44))
     ref_t = oracle.bilateral_at(f, idx, 20, 30.0, 30, eps=1e-7, truncated=True)
-    bounds = {"i16": TOL16, "fp16": 8 * TOL16, "bf16": 32 * TOL16}
-    for prec, bound in bounds.items():
-        out = _gpu_filter(f, 20, 30.0, N=30, precision=prec, weight_eps=1e-7, kahan=kahan)
-        assert np.max(np.abs(out - ref)) <= bound, prec
-        assert np.max(np.abs(out.ravel()[idx] - ref_t)) <= bound, prec
+    err_t = float(np.max(np.abs(out.ravel()[idx] - ref_t)))
+    print(f"{prec} kahan={kahan} 4096^2: max vs exact oracle {err_exact:.4g}, vs truncated oracle at "
+          f"the worst pixels {err_t:.4g}", flush=True)
+    assert err_exact <= TOL16 and err_t <= TOL16, (err_exact, err_t)
+
+
+@pytest.fixture(scope="module")
+def rect8192():
+    f = wl.rect_image(8192, 8192, seed=3)
+    return f, _gpu_filter(f, 32, 15.0, N=117)
+
+
+def test_rect8192_r32_fp32_and_truncation(rect8192):
+    """8192^2, r=32, sigma_r=15, N=117: the FP32 path against the exact oracle at sampled
+    pixels, and truncation at 1e-7 (28 of 59 folded orders) moving the exact result by far
+    less than the tolerance."""
+    f, out32 = rect8192
+    K, eps = plan_info(117, 1e-7)
+    assert K == 28 and abs(eps - 1.283e-7) < 1e-9
+    idx = _sample_idx(8192, 8192, 600, 33)
+    ref = oracle.bilateral_at(f, idx, 32, 15.0, 117)
+    ref_t = oracle.bilateral_at(f, idx, 32, 15.0, 117, eps=1e-7, truncated=True)
+    assert np.max(np.abs(ref - ref_t)) <= 1e-3
+    assert np.max(np.abs(out32.ravel()[idx] - ref)) <= TOL32
+
+
+@pytest.mark.parametrize("prec,kahan", [_form_param(p, k, MEETS_8192) for p, k in PRECISION_FORMS])
+def test_rect8192_r32_precision_form_worst_pixels(rect8192, prec, kahan):
+    """The precision form's own workload (8192^2, r=32, sigma_r=15, N=117, weights below 1e-7
+    dropped): the 2000 pixels where the 16-bit form departs most from the FP32 path, plus 600
+    random and border pixels, against the oracle's truncated kernel at 2e-3 T."""
+    f, out32 = rect8192
+    out = _gpu_filter(f, 32, 15.0, N=117, precision=prec, weight_eps=1e-7, kahan=kahan)
+    d32 = float(np.max(np.abs(out - out32)))
+    idx = np.union1d(_worst(np.abs(out - out32), 2000), _sample_idx(8192, 8192, 600, 33))
+    ref_t = oracle.bilateral_at(f, idx, 32, 15.0, 117, eps=1e-7, truncated=True)
+    err = float(np.max(np.abs(out.ravel()[idx] - ref_t)))
+    print(f"{prec} kahan={kahan} 8192^2: max vs FP32 {d32:.4g}, vs truncated oracle at the worst "
+          f"pixels {err:.4g}", flush=True)
+    assert err <= TOL16, err
 
 
 def test_fp64_rect4096_sampled():
@@ -223,24 +284,3 @@ def test_fp64_rect4096_sampled():
     assert np.max(np.abs(out.ravel()[idx] - ref)) <= TOL64
 
 
-def test_rect8192_r32_precision_form_sampled():
-    """8192x8192, r=32, sigma_r=15, N=117, weights below 1e-7 dropped (28 of 59 folded
-    orders), against the oracle's truncated kernel and the exact one.  The 16-bit
-    fixed-point stack meets 2e-3 T; bfloat16 and float16 stacks do not at this sigma_r
-    (normalisers fall to ~5) and are held to looser regression bounds."""
-    f = wl.rect_image(8192, 8192, seed=3)
-    K, eps = plan_info(117, 1e-7)
-    assert K == 28 and abs(eps - 1.283e-7) < 1e-9
-    idx = _sample_idx(8192, 8192, 600, 33)
-    ref_t = oracle.bilateral_at(f, idx, 32, 15.0, 117, eps=1e-7, truncated=True)
-    ref = oracle.bilateral_at(f, idx, 32, 15.0, 117)
-    # the truncation alone moves the result by far less than the tolerance
-    assert np.max(np.abs(ref - ref_t)) <= 1e-3
-    bounds = {"i16": TOL16, "fp16": 8 * TOL16, "bf16": 32 * TOL16}
-    for prec, bound in bounds.items():
-        for kahan in (False, True):
-            out = _gpu_filter(f, 32, 15.0, N=117, precision=prec, weight_eps=1e-7, kahan=kahan)
-            err = np.max(np.abs(out.ravel()[idx] - ref_t))
-            assert err <= bound, (prec, kahan, err)
-    out32 = _gpu_filter(f, 32, 15.0, N=117)
-    assert np.max(np.abs(out32.ravel()[idx] - ref)) <= TOL32

@@ -148,3 +148,25 @@ def test_poly_rect4096_sampled(eps):
         _, b = poly_plan_info(30.0, T, eps=eps)
         tol += b * 41 * 41 * T   # Q >= 1 (the centre pixel's own weight is 1)
     assert np.max(np.abs(out.ravel()[idx] - ref)) <= tol
+
+
+def test_coefficient_table_survives_batched_multipass_calls():
+    """The polynomial kernel keeps its coefficient table in a workspace buffer of the stream
+    and re-uploads it only when the plan or the buffer changes.  Batched calls with a
+    multi-pass image (their accumulator planes live in a workspace buffer of the same stream)
+    interleaved with two identical polynomial calls must leave it intact (regression: the two
+    once shared a buffer, and the second polynomial call read accumulator data as its
+    recurrence rows)."""
+    from paper_1107_4617_amd import bilateral_batched
+    f = wl.rect_image(64, 80, seed=7)
+    x = torch.from_numpy(f).cuda()
+    bimg = [torch.from_numpy(wl.gradient_image(300, 257, 9)).cuda()]
+    # sigma_r = 12: N_0 = 183, 92 folded orders, several 16-order passes
+    bilateral_batched(bimg, [5], [12.0], T)
+    y1 = bilateral(x, 4, 30.0, T, range_kernel="poly").clone()
+    bilateral_batched(bimg, [5], [12.0], T)
+    y2 = bilateral(x, 4, 30.0, T, range_kernel="poly")
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    ref = oracle.bilateral_poly(f, 4, 30.0, poly_order_for(30.0, T))
+    assert np.max(np.abs(y2.cpu().numpy() - ref)) <= TOL32
