@@ -154,6 +154,28 @@ int bilateral_shiftable_ex(const void *img, int H, int W, int radius, float sigm
                            void *out, const bsk_options *opt, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as bilateral_shiftable_ex, with the same kernels and launch shapes,
+ * making no device allocation.  The partial accumulators of a multi-pass
+ * launch (more folded orders than one pass holds) live in a fixed 128 MiB
+ * device array of the library instead of the per-stream workspace: two FP32
+ * planes of up to 4096 x 4096 pixels, or two FP64 planes of up to 4096 x 2048.
+ *   img, out, H, W, radius, sigma_r, T, opt, stream: as bilateral_shiftable_ex
+ * Supported: the raised-cosine range kernel with the box spatial kernel, in
+ * every precision; the separable spatial kernel and the polynomial range
+ * kernel return BSK_EUNSUPPORTED.  A multi-pass request whose accumulators
+ * exceed the array returns BSK_ENOMEM before anything is queued.
+ * Each device holds one copy of the array, from the first call on it until
+ * the process ends, and every call on a device shares it: calls that overlap
+ * in time on one device (on different streams, or from different threads)
+ * race and must be ordered by the caller.  Nothing in the array needs to start
+ * at zero.
+ */
+int bilateral_shiftable_noalloc(const void *img, int H, int W, int radius, float sigma_r, float T,
+                                void *out, const bsk_options *opt, void *stream);
+
+/*
  * Two-pixel-patch non-local means (Section 5, the Discussion, with p = 2
  * patch pixels u_1 = 0 and u_2 = (uy, ux)): the bilateral filter of eq. (3)
  * with the range kernel comparing the patches {x, x + u_2} and {y, y + u_2},

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "BSK_OK", -1: "BSK_EINVAL", -2: "BSK_ERANGE", -3: "BSK_ENOMEM
 
 # Every symbol include/bsk.h declares.
 EXPORTS = [
-    "bilateral_shiftable", "bilateral_shiftable_ex", "bilateral_shiftable_nlm2", "bilateral_shiftable_train",
+    "bilateral_shiftable", "bilateral_shiftable_ex", "bilateral_shiftable_noalloc", "bilateral_shiftable_nlm2", "bilateral_shiftable_train",
     "bilateral_shiftable_backward", "bilateral_shiftable_batched", "bilateral_shiftable_batched_graph",
     "bsk_order_for", "bsk_plan_info", "bsk_truncation_error", "bsk_poly_order_for", "bsk_poly_plan_info",
     "bsk_autotune", "bsk_set_workspace_limit", "bsk_last_error", "bsk_release", "bsk_version",
@@ -75,6 +75,7 @@ def load():
     sig = {
         "bilateral_shiftable": (_i, [_vp, _i, _i, _i, _f, _f, _vp]),
         "bilateral_shiftable_ex": (_i, [_vp, _i, _i, _i, _f, _f, _vp, ctypes.POINTER(Options), _vp]),
+        "bilateral_shiftable_noalloc": (_i, [_vp, _i, _i, _i, _f, _f, _vp, ctypes.POINTER(Options), _vp]),
         "bilateral_shiftable_nlm2": (_i, [_vp, _i, _i, _i, _f, _f, _i, _i, _i, _i, _f, _vp, ctypes.POINTER(Options),
                                           _vp]),
         "bilateral_shiftable_train": (_i, [_vp, _i, _i, _i, _f, _f, ctypes.POINTER(Options), _vp, _vp, _vp]),
