@@ -170,20 +170,32 @@ struct Chain {
     AT c, s, cp, sp, a2;   // current, previous, 2 cos(delta g)
     __device__ __forceinline__ void start(bool valid, AT g, AT om0, AT dlt, int mode)
     {
-        AT c0, s0, cd, sd;
         if (mode <= 1) {
             // the half step angle y = delta g / 2 (= omega_0 g when omega_0 = delta / 2),
             // then the step by the double-angle formulas
             AT sh, ch;
             sc_small(AT(0.5) * dlt * g, &sh, &ch);
-            cd = fmat(AT(-2) * sh, sh, AT(1));
-            sd = AT(2) * sh * ch;
-            c0 = mode == 0 ? AT(1) : ch;
-            s0 = mode == 0 ? AT(0) : sh;
-        } else {
-            sc(om0 * g, &s0, &c0);
-            sc_step(dlt * g, &sd, &cd);
+            const AT cd = fmat(AT(-2) * sh, sh, AT(1));
+            a2 = AT(2) * cd;
+            if (mode == 0) {
+                // omega_0 = 0: (c, s) = (1, 0) and the order before it at -delta g
+                const AT sd = AT(2) * sh * ch;
+                c = valid ? AT(1) : AT(0);
+                s = AT(0);
+                cp = valid ? cd : AT(0);
+                sp = valid ? -sd : AT(0);
+            } else {
+                // omega_0 = delta / 2: (c, s) = (ch, sh) and the order before it at -y
+                c = valid ? ch : AT(0);
+                s = valid ? sh : AT(0);
+                cp = c;
+                sp = -s;
+            }
+            return;
         }
+        AT c0, s0, cd, sd;
+        sc(om0 * g, &s0, &c0);
+        sc_step(dlt * g, &sd, &cd);
         const AT z = valid ? AT(1) : AT(0);
         c = z * c0;
         s = z * s0;
@@ -191,10 +203,13 @@ struct Chain {
         sp = z * (s0 * cd - c0 * sd);
         a2 = AT(2) * cd;
     }
+    // S0: the current sine value is exactly zero (the zero frequency), so the
+    // next one is -sp without a multiply-add on the zero
+    template <bool S0 = false>
     __device__ __forceinline__ void step()
     {
         const AT cn = fmat(a2, c, -cp);
-        const AT sn = fmat(a2, s, -sp);
+        const AT sn = S0 ? -sp : fmat(a2, s, -sp);
         cp = c;
         sp = s;
         c = cn;
@@ -299,6 +314,14 @@ struct PolForward {
         const AT vc = v * C, vs = v * S;
         acc[0] = fmat(vc, B[0], fmat(vs, B[1], acc[0]));
         acc[1] = fmat(vc, B[2], fmat(vs, B[3], acc[1]));
+    }
+    // the zero frequency: S = 0, so only the cosine members contribute
+    template <typename AT>
+    __device__ static void recombine_s0(AT v, AT C, const AT *B, AT *acc)
+    {
+        const AT vc = v * C;
+        acc[0] = fmat(vc, B[0], acc[0]);
+        acc[1] = fmat(vc, B[2], acc[1]);
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
@@ -810,6 +833,10 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     // POL::START >= 0: one pass (K <= KR) whose chain start mode is that constant
     constexpr int CSTART = POL::START;
     const int Kloop = CSTART >= 0 ? 1 : gm.K;
+    // Order m of a one-pass launch with the chain start of even N is the zero
+    // frequency: its sine channels vanish identically, so their sums, updates
+    // and recombination terms are skipped (m is a constant of the unrolled loops).
+    auto zero_sine = [](int m) { return CSTART == 0 && m == 0; };
     for (int m0 = 0; m0 < Kloop; m0 += KR) {
         const bool first = (m0 == 0);
         const bool last = CSTART >= 0 || (m0 + KR >= gm.K);
@@ -873,13 +900,14 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 chain_start<POL>(ch, colok, aux, om0, dlt, smode, om1, d1);
 #pragma unroll
                 for (int m = 0; m < KR; ++m) {
+                    const bool zs = zero_sine(m);
                     chain_restart<POL>(ch, m);
                     const AT C = quant<QUANT>(ch.c), S = quant<QUANT>(ch.s);
 #pragma unroll
                     for (int p = 0; p < NPAIR; ++p) {
                         if constexpr (PLAIN) {
                             V[m][2 * p] = fmat(kp[p], C, V[m][2 * p]);
-                            V[m][2 * p + 1] = fmat(kp[p], S, V[m][2 * p + 1]);
+                            if (!zs) V[m][2 * p + 1] = fmat(kp[p], S, V[m][2 * p + 1]);
                         }
                         if constexpr (NSC > 0) {
 #pragma unroll
@@ -891,7 +919,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                             }
                         }
                     }
-                    ch.step();
+                    if (zs) ch.template step<true>();
+                    else ch.step();
                 }
             }
         }
@@ -969,10 +998,14 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                             rlo[q] = VbR[q * RS + plo];
                         }
                     }
-                    if (actH && walker) {
+                    // Read whether or not the H stage runs this interval (every lane of
+                    // this launch shape is a walker and its chunk lies inside the
+                    // buffer): a conditional read would make loc[] a value carried
+                    // from one interval to the next, which the compiler keeps with
+                    // a register copy per element.
+                    static_assert(!JOINT || ALLWALK, "joint reads assume every lane walks");
 #pragma unroll
-                        for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
-                    }
+                    for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
                 }
                 // ---- R stage: box sums of the orders sR KL .. of row iR, recombined
                 if (actR && outlane) {
@@ -1025,6 +1058,13 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         if constexpr (IsPatch2<POL>::value) v = ((ConstPtr<float>)gm.p2_vf)[m0 + m];
                         else v = weight<AT>(gm, m0 + m);
                         const AT vom = v * (om0 + (AT)m * dlt);
+                        if constexpr (CSTART == 0) {
+                            if (zero_sine(m)) {
+                                POL::template recombine_s0<AT>(v, quant<QUANT>(cc.c), B, acc);
+                                cc.template step<true>();
+                                continue;
+                            }
+                        }
                         POL::template recombine<AT>(v, vom, quant<QUANT>(cc.c), quant<QUANT>(cc.s), B, auxc, acc);
                         cc.step();
                     }
@@ -1098,12 +1138,13 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         chain_restart<POL>(co, m);
                         const AT Ci = quant<QUANT>(ci.c), Si = quant<QUANT>(ci.s);
                         const AT Co = quant<QUANT>(co.c), So = quant<QUANT>(co.s);
+                        const bool zs = zero_sine(m);
 #pragma unroll
                         for (int p = 0; p < NPAIR; ++p) {
                             if constexpr (KAHAN) {
                                 const AT x[2] = {ki[p] * Ci - ko[p] * Co, ki[p] * Si - ko[p] * So};
 #pragma unroll
-                                for (int e = 0; e < 2; ++e) {
+                                for (int e = 0; e < (zs ? 1 : 2); ++e) {
                                     const int c = 2 * p + e;
                                     const AT y = x[e] - Cmp[m][c];
                                     const AT s = V[m][c] + y;
@@ -1113,7 +1154,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                             } else {
                                 if constexpr (PLAIN) {
                                     V[m][2 * p] = fmat(-ko[p], Co, fmat(ki[p], Ci, V[m][2 * p]));
-                                    V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
+                                    if (!zs) V[m][2 * p + 1] = fmat(-ko[p], So, fmat(ki[p], Si, V[m][2 * p + 1]));
                                 }
                                 if constexpr (NSC > 0) {
 #pragma unroll
@@ -1156,8 +1197,13 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 }
                             }
                         }
-                        ci.step();
-                        co.step();
+                        if (zs) {
+                            ci.template step<true>();
+                            co.template step<true>();
+                        } else {
+                            ci.step();
+                            co.step();
+                        }
                     }
                 }
 
