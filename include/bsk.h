@@ -247,8 +247,14 @@ typedef struct {
  * bilateral_shiftable_ex (eq. (3) through Algorithm 2, box spatial kernel,
  * raised-cosine range kernel of eq. (6) at its own order); gathering many
  * images into one launch has no counterpart in the paper.  descs is a HOST array of B descriptors.  Work
- * units (image, strip, row segment) are claimed from a device work counter;
- * the launch shape comes from the autotuner (bsk_autotune) when tuned.
+ * units (image, strip, row segment) are claimed from a device work counter.
+ * Launch shape: opt->block, opt->strip_h (rows per unit) and opt->order_chunk
+ * (orders per pass: the batched kernel's 256/512/1024-lane pass of 16/8/4
+ * orders or its half) when non-zero; otherwise the shapes that
+ * bsk_autotune_batched measured for the batch's largest radius bucket (lanes)
+ * and for each image's (radius bucket, order bucket) (rows, orders per pass);
+ * otherwise the defaults (lanes from the largest radius, 96 rows, the pass
+ * size that pads fewer orders).  bsk_batched_shape reports the choice.
  * The descriptor table is staged through a library-owned device buffer, so
  * consecutive batched calls on one device must be ordered on one stream.
  */
@@ -263,6 +269,43 @@ int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T,
  */
 int bilateral_shiftable_batched_graph(const bsk_image_desc *descs, int B, float T,
                                       const bsk_options *opt, int key, void *stream);
+
+/*
+ * Launch shape the batched entry points would use for these descriptors and
+ * options (host only, nothing is queued): lanes per workgroup, and per
+ * descriptor (in the order given) the rows per work unit (at most the image
+ * height) and the orders per pass.  block, rows and chunk are nullable; rows
+ * and chunk hold B entries.  Errors as for bilateral_shiftable_batched.
+ */
+int bsk_batched_shape(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, int *block,
+                      int *rows, int *chunk);
+
+/*
+ * Autotuner of the batched launch (strip and tile sizes of the persistent
+ * kernel).  Times bilateral_shiftable_batched on these descriptors (their out
+ * buffers are overwritten many times; the stream is synchronised): first the
+ * lanes per workgroup that fit the largest radius, then, bucket by bucket
+ * (clamped radius bucket 0, 1, 2-3, 4-7, ...; folded-order bucket 1, 2, 3-4,
+ * 5-8, ...; buckets with the most pixels first), the rows per work unit in
+ * {32, 48, 64, 96, 128, 192, 256} and the two pass sizes, keeping each change
+ * that makes the whole launch faster.  The result is stored per bucket and
+ * used by later batched calls whose options leave block, strip_h and
+ * order_chunk at 0.  opt's block, strip_h and order_chunk are ignored.
+ * `path` (nullable) names the JSON-lines cache file (shared with
+ * bsk_autotune) that is read first and rewritten with the result.
+ * best_block and best_ms (nullable) receive the lanes chosen and the fastest
+ * launch time in milliseconds.
+ */
+int bsk_autotune_batched(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, const char *path,
+                         void *stream, int *best_block, double *best_ms);
+
+/* The autotuners' cache (single-image and batched shapes), host only:
+ * load adds the entries of a JSON-lines file (BSK_EINVAL if it cannot be
+ * read), save writes every entry held (BSK_EINVAL if it cannot be written),
+ * clear forgets them all (and stops BSK_TUNE_CACHE from being read later). */
+int bsk_tune_cache_load(const char *path);
+int bsk_tune_cache_save(const char *path);
+int bsk_tune_cache_clear(void);
 
 /* N_0 = ceil((2T / (pi sigma_r))^2) (Section 3.1); -1 on invalid input. */
 int bsk_order_for(float sigma_r, float T);

@@ -8,8 +8,9 @@ by fused HIP kernels (libbsk.so) behind a
 C ABI (include/bsk.h).  The torch-facing calls live in `filter`; importing this
 package does not touch the GPU.
 """
-from .filter import (BilateralFunction, ShiftableBilateral, autotune, bilateral, bilateral_backward,  # noqa: F401
-                     bilateral_batched, bilateral_train, nlm2, order_for, plan_info, poly_order_for,
-                     poly_plan_info, release, spatial_filter, spatial_sigma_for)
+from .filter import (BilateralFunction, ShiftableBilateral, autotune, autotune_batched,  # noqa: F401
+                     batched_shape, bilateral, bilateral_backward, bilateral_batched, bilateral_train, nlm2,
+                     order_for, plan_info, poly_order_for, poly_plan_info, release, spatial_filter,
+                     spatial_sigma_for, tune_cache_clear, tune_cache_load, tune_cache_save)
 
 __version__ = "0.1.0"

@@ -32,7 +32,8 @@ EXPORTS = [
     "bilateral_shiftable", "bilateral_shiftable_ex", "bilateral_shiftable_noalloc", "bilateral_shiftable_nlm2", "bilateral_shiftable_train",
     "bilateral_shiftable_backward", "bilateral_shiftable_batched", "bilateral_shiftable_batched_graph",
     "bsk_order_for", "bsk_plan_info", "bsk_truncation_error", "bsk_poly_order_for", "bsk_poly_plan_info",
-    "bsk_autotune", "bsk_set_workspace_limit", "bsk_last_error", "bsk_release", "bsk_version",
+    "bsk_autotune", "bsk_batched_shape", "bsk_autotune_batched", "bsk_tune_cache_load", "bsk_tune_cache_save",
+    "bsk_tune_cache_clear", "bsk_set_workspace_limit", "bsk_last_error", "bsk_release", "bsk_version",
 ]
 
 
@@ -91,6 +92,13 @@ def load():
         "bsk_poly_plan_info": (_i, [_i, _f, _f, _d, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
         "bsk_autotune": (_i, [_vp, _i, _i, _i, _f, _f, _vp, ctypes.POINTER(Options), ctypes.c_char_p, _vp,
                               ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+        "bsk_batched_shape": (_i, [ctypes.POINTER(ImageDesc), _i, _f, ctypes.POINTER(Options), ctypes.POINTER(_i),
+                                   ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "bsk_autotune_batched": (_i, [ctypes.POINTER(ImageDesc), _i, _f, ctypes.POINTER(Options), ctypes.c_char_p,
+                                      _vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+        "bsk_tune_cache_load": (_i, [ctypes.c_char_p]),
+        "bsk_tune_cache_save": (_i, [ctypes.c_char_p]),
+        "bsk_tune_cache_clear": (_i, []),
         "bsk_set_workspace_limit": (_i, [ctypes.c_longlong]),
         "bsk_last_error": (ctypes.c_char_p, []),
         "bsk_release": (_i, []),

@@ -25,11 +25,62 @@ struct BatchPlan {
     long long ws_elems = 0;
     int total_units = 0;
     int block = 256;
+    std::vector<int> rows, chunk;   // per descriptor, in descriptor order: rows per unit, orders per pass
+    std::vector<int> rbucket, kbucket;
 };
 
 constexpr int kBatchRows = 96;   // default output rows per work unit (64: 1% slower on the 256-image batch)
 
-int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt, BatchPlan *bp)
+// Tuning buckets of the batched launch: clamped radius 0, 1, 2-3, 4-7, 8-15,
+// ... (bit length) and folded orders 1, 2, 3-4, 5-8, 9-16, ... (ceil log2).
+int radius_bucket(int rh)
+{
+    int b = 0;
+    while (b < 30 && (1 << b) <= rh) ++b;
+    return b;
+}
+int order_bucket(int K)
+{
+    int b = 0;
+    while (b < 30 && (1 << b) < K) ++b;
+    return b;
+}
+
+// Batched launch shapes measured by bsk_autotune_batched: per (radius bucket,
+// order bucket, precision, lanes) the rows per work unit and orders per pass,
+// and per (largest radius bucket of a batch, precision) the lanes per workgroup.
+struct BatchTuneKey {
+    int rb, kb, prec, block;
+    bool operator<(const BatchTuneKey &o) const
+    {
+        return std::tie(rb, kb, prec, block) < std::tie(o.rb, o.kb, o.prec, o.block);
+    }
+};
+struct BatchTuneVal {
+    int S, kc;
+    double ms;
+};
+struct BatchBlockKey {
+    int rb, prec;
+    bool operator<(const BatchBlockKey &o) const { return std::tie(rb, prec) < std::tie(o.rb, o.prec); }
+};
+struct BatchBlockVal {
+    int block;
+    double ms;
+};
+// What the tuner's sweep imposes on build_batch: lanes (0: the usual choice),
+// per (radius bucket, order bucket) rows and orders per pass, and whether the
+// measured table is consulted at all.
+struct BatchShapeOverride {
+    bool use_table = true;
+    int block = 0;
+    std::map<std::pair<int, int>, std::pair<int, int>> shape;
+};
+bool batch_tuned_block(int rb, int prec, int *block);
+bool batch_tuned_shape(int rb, int kb, int prec, int block, int *S, int *kc);
+
+int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt, BatchPlan *bp,
+                const BatchShapeOverride *ovr = nullptr)
 {
     if (!d || B < 1) return fail(BSK_EINVAL, "need at least one descriptor");
     if (!finite_pos(T)) return fail(BSK_EINVAL, "T must be finite and > 0");
@@ -42,10 +93,12 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     if (o.pitch_in || o.pitch_out) return fail(BSK_EUNSUPPORTED, "the batched path needs dense pitch");
     if (o.strip_h < 0 || !(o.weight_eps >= 0.0)) return fail(BSK_EINVAL, "bad options");
 
+    if (o.order_chunk < 0) return fail(BSK_EINVAL, "bad options");
     struct Item {
         bsk::BatchImage im;
         std::vector<double> v;
         double cost;
+        int idx, rb, kb;
     };
     std::vector<Item> items;
     items.reserve(B);
@@ -80,23 +133,60 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         it.im.delta = pl.delta;
         it.im.start_mode = pl.start_mode;
         it.v.assign(pl.v, pl.v + pl.K);
+        it.idx = b;
+        it.rb = radius_bucket(std::max(it.im.rh, it.im.rv));
+        it.kb = order_bucket(pl.K);
         max_rh = std::max(max_rh, it.im.rh);
         items.push_back(std::move(it));
     }
+    const bool table = !ovr || ovr->use_table;
+    constexpr int prec = BSK_FP32;
     int block = o.block;
+    if (block == 0 && ovr && ovr->block) block = ovr->block;
+    if (block == 0 && table) {
+        int rbmax = 0;
+        for (const auto &it : items) rbmax = std::max(rbmax, it.rb);
+        int tb = 0;
+        if (batch_tuned_block(rbmax, prec, &tb) && max_rh <= bsk::max_radius_batched(tb)) block = tb;
+    }
     if (block == 0) block = (max_rh <= 64) ? 256 : (max_rh <= 128 ? 512 : 1024);
     if (block != 256 && block != 512 && block != 1024) return fail(BSK_EINVAL, "block must be 256, 512 or 1024");
     if (max_rh > bsk::max_radius_batched(block))
         return fail(BSK_EUNSUPPORTED, "clamped radius %d too large for a %d-lane strip", max_rh, block);
     const int kfull = bsk::chunk_batched_f32(block);
-    const int rows = o.strip_h > 0 ? o.strip_h : kBatchRows;
+    if (o.order_chunk != 0 && o.order_chunk != kfull && o.order_chunk != kfull / 2)
+        return fail(BSK_EINVAL, "order_chunk %d is not a pass size (%d or %d) of the %d-lane batched kernel",
+                    o.order_chunk, kfull, kfull / 2, block);
+    bp->rows.assign(B, 0);
+    bp->chunk.assign(B, 0);
+    bp->rbucket.assign(B, 0);
+    bp->kbucket.assign(B, 0);
     for (auto &it : items) {
         const int Wt = block - 2 * it.im.rh;
         it.im.strips = (it.im.W + Wt - 1) / Wt;
+        // rows per unit and orders per pass: the options, else the tuner's sweep,
+        // else the measured table, else the defaults (the full pass or its half,
+        // whichever pads fewer orders for the cost)
+        int rows = kBatchRows, kc = pick_chunk(it.im.K, kfull);
+        int ts = 0, tk = 0;
+        if (ovr) {
+            auto f = ovr->shape.find({it.rb, it.kb});
+            if (f != ovr->shape.end()) {
+                ts = f->second.first;
+                tk = f->second.second;
+            }
+        }
+        if (!ts && table) batch_tuned_shape(it.rb, it.kb, prec, block, &ts, &tk);
+        if (ts > 0) rows = ts;
+        if (tk == kfull || tk == kfull / 2) kc = tk;
+        if (o.strip_h > 0) rows = o.strip_h;
+        if (o.order_chunk > 0) kc = o.order_chunk;
         it.im.S = std::min(rows, it.im.H);
-        // per image: the full pass or its half, whichever pads fewer orders for the cost
-        it.im.kc = pick_chunk(it.im.K, kfull);
-        const int kc = it.im.kc;
+        it.im.kc = kc;
+        bp->rows[it.idx] = it.im.S;
+        bp->chunk[it.idx] = kc;
+        bp->rbucket[it.idx] = it.rb;
+        bp->kbucket[it.idx] = it.kb;
         const int segs = (it.im.H + it.im.S - 1) / it.im.S;
         // work of one unit ~ lanes x (rows + window) x (padded orders + per-pass cost)
         const int passes = (it.im.K + kc - 1) / kc;
@@ -282,38 +372,94 @@ struct TuneVal {
     int block, S, kc;
     double ms;
 };
-std::mutex g_tune_mu;
+std::mutex g_tune_mu;   // guards every table below
 std::map<TuneKey, TuneVal> g_tune;
+std::map<BatchTuneKey, BatchTuneVal> g_btune;
+std::map<BatchBlockKey, BatchBlockVal> g_bblock;
 bool g_tune_loaded = false;
 
-void load_tune_file(const char *path)
+// Cache file: JSON lines of three kinds (single-image shapes, batched shapes
+// per bucket, batched lanes per largest radius bucket).  Returns false if the
+// file cannot be opened; lines of no known kind are skipped.
+bool load_tune_file(const char *path)
 {
     FILE *f = path ? std::fopen(path, "r") : nullptr;
-    if (!f) return;
+    if (!f) return false;
     char line[256];
     while (std::fgets(line, sizeof(line), f)) {
         TuneKey k;
         TuneVal v;
+        BatchTuneKey bk;
+        BatchTuneVal bv;
+        BatchBlockKey lk;
+        BatchBlockVal lv;
         if (std::sscanf(line, "{\"rh\": %d, \"K\": %d, \"H\": %d, \"W\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, "
                               "\"kc\": %d, \"ms\": %lf}",
                         &k.rh, &k.K, &k.H, &k.W, &k.prec, &v.block, &v.S, &v.kc, &v.ms) == 9)
             g_tune[k] = v;
+        else if (std::sscanf(line, "{\"batched_rb\": %d, \"kb\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, "
+                                   "\"kc\": %d, \"ms\": %lf}",
+                             &bk.rb, &bk.kb, &bk.prec, &bk.block, &bv.S, &bv.kc, &bv.ms) == 7)
+            g_btune[bk] = bv;
+        else if (std::sscanf(line, "{\"batched_block_rb\": %d, \"prec\": %d, \"block\": %d, \"ms\": %lf}", &lk.rb,
+                             &lk.prec, &lv.block, &lv.ms) == 4)
+            g_bblock[lk] = lv;
     }
     std::fclose(f);
+    return true;
 }
 
-void save_tune_file(const char *path)
+bool save_tune_file(const char *path)
 {
-    if (!path) return;
+    if (!path) return false;
     FILE *f = std::fopen(path, "w");
-    if (!f) return;
+    if (!f) return false;
     for (auto &kv : g_tune)
         std::fprintf(f,
                      "{\"rh\": %d, \"K\": %d, \"H\": %d, \"W\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, "
                      "\"kc\": %d, \"ms\": %.6f}\n",
                      kv.first.rh, kv.first.K, kv.first.H, kv.first.W, kv.first.prec, kv.second.block,
                      kv.second.S, kv.second.kc, kv.second.ms);
-    std::fclose(f);
+    for (auto &kv : g_btune)
+        std::fprintf(f, "{\"batched_rb\": %d, \"kb\": %d, \"prec\": %d, \"block\": %d, \"S\": %d, \"kc\": %d, "
+                        "\"ms\": %.6f}\n",
+                     kv.first.rb, kv.first.kb, kv.first.prec, kv.first.block, kv.second.S, kv.second.kc,
+                     kv.second.ms);
+    for (auto &kv : g_bblock)
+        std::fprintf(f, "{\"batched_block_rb\": %d, \"prec\": %d, \"block\": %d, \"ms\": %.6f}\n", kv.first.rb,
+                     kv.first.prec, kv.second.block, kv.second.ms);
+    const bool ok = std::ferror(f) == 0;
+    return std::fclose(f) == 0 && ok;
+}
+
+// The environment's cache file, read once at first use (caller holds g_tune_mu).
+void ensure_tune_loaded()
+{
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        load_tune_file(std::getenv("BSK_TUNE_CACHE"));
+    }
+}
+
+bool batch_tuned_block(int rb, int prec, int *block)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    ensure_tune_loaded();
+    auto it = g_bblock.find(BatchBlockKey{rb, prec});
+    if (it == g_bblock.end()) return false;
+    *block = it->second.block;
+    return true;
+}
+
+bool batch_tuned_shape(int rb, int kb, int prec, int block, int *S, int *kc)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    ensure_tune_loaded();
+    auto it = g_btune.find(BatchTuneKey{rb, kb, prec, block});
+    if (it == g_btune.end()) return false;
+    *S = it->second.S;
+    *kc = it->second.kc;
+    return true;
 }
 
 }  // namespace
@@ -324,10 +470,7 @@ namespace host {
 bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S, int *kc)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (!g_tune_loaded) {
-        g_tune_loaded = true;
-        load_tune_file(std::getenv("BSK_TUNE_CACHE"));
-    }
+    ensure_tune_loaded();
     auto it = g_tune.find(TuneKey{rh, K, H, W, prec});
     if (it == g_tune.end()) return false;
     *block = it->second.block;
@@ -339,12 +482,27 @@ bool tuned_shape(int rh, int K, int H, int W, int prec, int *block, int *S, int 
 }  // namespace host
 }  // namespace bsk
 
+namespace {
+int run_batched(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, void *stream,
+                const BatchShapeOverride *ovr);
+}
+
 extern "C" {
 
 int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, void *stream)
 {
+    return run_batched(descs, B, T, opt, stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+int run_batched(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, void *stream,
+                const BatchShapeOverride *ovr)
+{
     BatchPlan bp;
-    int st = build_batch(descs, B, T, opt, &bp);
+    int st = build_batch(descs, B, T, opt, &bp, ovr);
     if (st) return st;
     size_t off_v, off_f, off_c;
     std::vector<char> host;
@@ -365,6 +523,10 @@ int bilateral_shiftable_batched(const bsk_image_desc *descs, int B, float T, con
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     return BSK_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int bilateral_shiftable_batched_graph(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, int key,
                                       void *stream)
@@ -482,10 +644,7 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     if (st) return st;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        if (!g_tune_loaded) {
-            g_tune_loaded = true;
-            load_tune_file(std::getenv("BSK_TUNE_CACHE"));
-        }
+        ensure_tune_loaded();
         load_tune_file(path);
     }
     hipEvent_t e0, e1;
@@ -540,6 +699,167 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     if (best_rows) *best_rows = best.S;
     if (best_chunk) *best_chunk = best.kc;
     if (best_ms) *best_ms = best.ms;
+    return BSK_OK;
+}
+
+int bsk_batched_shape(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, int *block, int *rows,
+                      int *chunk)
+{
+    BatchPlan bp;
+    const int st = build_batch(descs, B, T, opt, &bp);
+    if (st) return st;
+    if (block) *block = bp.block;
+    for (int b = 0; b < B; ++b) {
+        if (rows) rows[b] = bp.rows[b];
+        if (chunk) chunk[b] = bp.chunk[b];
+    }
+    return BSK_OK;
+}
+
+int bsk_autotune_batched(const bsk_image_desc *descs, int B, float T, const bsk_options *opt, const char *path,
+                         void *stream, int *best_block, double *best_ms)
+{
+    bsk_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    o.block = 0;
+    o.strip_h = 0;
+    o.order_chunk = 0;
+    // the plan with the defaults validates the request before anything is timed
+    BatchShapeOverride ovr;
+    ovr.use_table = false;
+    BatchPlan base;
+    int st = build_batch(descs, B, T, &o, &base, &ovr);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        ensure_tune_loaded();
+        load_tune_file(path);
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(BSK_EHIP, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(BSK_EHIP, "hipEventCreate failed");
+    }
+    // one warm-up launch, then the fastest of three
+    auto time_it = [&](const BatchShapeOverride &v, double *ms) -> int {
+        double best = 1e30;
+        for (int rep = 0; rep < 4; ++rep) {
+            hipError_t e = hipEventRecord(e0, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            const int r = run_batched(descs, B, T, &o, stream, &v);
+            if (r) return r;
+            e = hipEventRecord(e1, (hipStream_t)stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            float t = 0.f;
+            hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0 && t < best) best = t;
+        }
+        *ms = best;
+        return BSK_OK;
+    };
+    int max_rh = 0, rbmax = 0;
+    // buckets present, with their pixel counts (most pixels first)
+    std::map<std::pair<int, int>, double> pix;
+    std::map<std::pair<int, int>, int> hmax;
+    for (int b = 0; b < B; ++b) {
+        const int rh = std::min(descs[b].radius, descs[b].W - 1);
+        max_rh = std::max(max_rh, rh);
+        rbmax = std::max(rbmax, base.rbucket[b]);
+        const auto key = std::make_pair(base.rbucket[b], base.kbucket[b]);
+        pix[key] += (double)descs[b].H * descs[b].W;
+        hmax[key] = std::max(hmax[key], descs[b].H);
+    }
+    std::vector<std::pair<double, std::pair<int, int>>> order;
+    for (auto &kv : pix) order.push_back({kv.second, kv.first});
+    std::sort(order.begin(), order.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+
+    // lanes per workgroup first (with the default rows and passes), then a
+    // coordinate sweep over the buckets' rows and pass sizes at those lanes
+    double best = 1e30;
+    int bblock = 0;
+    for (int blk : {256, 512, 1024}) {
+        if (max_rh > bsk::max_radius_batched(blk)) continue;
+        BatchShapeOverride v = ovr;
+        v.block = blk;
+        double ms = 0.0;
+        st = time_it(v, &ms);
+        if (st) break;
+        if (ms < best) {
+            best = ms;
+            bblock = blk;
+        }
+    }
+    ovr.block = bblock;
+    const int kfull = bblock ? bsk::chunk_batched_f32(bblock) : 0;
+    const int rows_c[7] = {32, 48, 64, 96, 128, 192, 256};
+    for (size_t q = 0; !st && q < order.size(); ++q) {
+        const auto key = order[q].second;
+        std::pair<int, int> keep{0, 0};
+        for (int si = 0; si < 7; ++si) {
+            const int S = rows_c[si];
+            // units taller than the bucket's tallest image are all the same shape
+            if (si > 0 && rows_c[si - 1] >= hmax[key]) break;
+            for (int kc : {kfull, kfull / 2}) {
+                BatchShapeOverride v = ovr;
+                v.shape[key] = {S, kc};
+                double ms = 0.0;
+                st = time_it(v, &ms);
+                if (st) break;
+                if (ms < best) {
+                    best = ms;
+                    keep = {S, kc};
+                }
+            }
+            if (st) break;
+        }
+        if (keep.first) ovr.shape[key] = keep;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    // the lanes and the buckets' shapes the sweep settled on (buckets it left
+    // at the defaults record nothing), stored for later calls and written to `path`
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_bblock[BatchBlockKey{rbmax, BSK_FP32}] = BatchBlockVal{bblock, best};
+        for (auto &kv : ovr.shape)
+            g_btune[BatchTuneKey{kv.first.first, kv.first.second, BSK_FP32, bblock}] =
+                BatchTuneVal{kv.second.first, kv.second.second, best};
+        if (path && !save_tune_file(path)) return fail(BSK_EINVAL, "cannot write the tune cache %s", path);
+    }
+    if (best_block) *best_block = bblock;
+    if (best_ms) *best_ms = best;
+    return BSK_OK;
+}
+
+int bsk_tune_cache_load(const char *path)
+{
+    if (!path) return fail(BSK_EINVAL, "null path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    ensure_tune_loaded();
+    if (!load_tune_file(path)) return fail(BSK_EINVAL, "cannot read the tune cache %s", path);
+    return BSK_OK;
+}
+
+int bsk_tune_cache_save(const char *path)
+{
+    if (!path) return fail(BSK_EINVAL, "null path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    ensure_tune_loaded();
+    if (!save_tune_file(path)) return fail(BSK_EINVAL, "cannot write the tune cache %s", path);
+    return BSK_OK;
+}
+
+int bsk_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_loaded = true;   // the environment's file is not re-read after a clear
+    g_tune.clear();
+    g_btune.clear();
+    g_bblock.clear();
     return BSK_OK;
 }
 

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import math
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import torch
 
@@ -16,6 +16,7 @@ from . import _lib
 
 __all__ = ["bilateral", "nlm2", "spatial_filter", "spatial_sigma_for", "bilateral_train", "bilateral_backward",
            "bilateral_batched", "order_for", "plan_info", "poly_order_for", "poly_plan_info", "autotune",
+           "batched_shape", "autotune_batched", "tune_cache_load", "tune_cache_save", "tune_cache_clear",
            "BilateralFunction", "ShiftableBilateral", "release"]
 
 
@@ -210,16 +211,8 @@ def bilateral_backward(img: torch.Tensor, grad_out: torch.Tensor, radius: int, s
     return gi, gs
 
 
-def bilateral_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas: Sequence[float],
-                      T: float = 255.0, Ns: Optional[Sequence[int]] = None, outs=None,
-                      graph_key: Optional[int] = None, strip_h: int = 0):
-    """Filters many images (any sizes, radii, sigma_r) in one persistent launch.
-
-    With graph_key set, the first call captures the launch into a HIP graph on the
-    current (non-default) stream and later calls with the same key replay it."""
+def _batch_descs(imgs, outs, radii, sigmas, Ns):
     B = len(imgs)
-    if outs is None:
-        outs = [torch.empty_like(x) for x in imgs]
     descs = (_lib.ImageDesc * B)()
     for b, (x, o) in enumerate(zip(imgs, outs)):
         _check_image(x, f"imgs[{b}]")
@@ -230,7 +223,23 @@ def bilateral_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas
         descs[b].radius = int(radii[b])
         descs[b].sigma_r = float(sigmas[b])
         descs[b].N = -1 if Ns is None or Ns[b] is None else int(Ns[b])
-    opt = _options(strip_h=strip_h)
+    return descs
+
+
+def bilateral_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas: Sequence[float],
+                      T: float = 255.0, Ns: Optional[Sequence[int]] = None, outs=None,
+                      graph_key: Optional[int] = None, strip_h: int = 0, block: int = 0, order_chunk: int = 0):
+    """Filters many images (any sizes, radii, sigma_r) in one persistent launch.
+
+    With graph_key set, the first call captures the launch into a HIP graph on the
+    current (non-default) stream and later calls with the same key replay it.
+    block, strip_h and order_chunk left at 0 take the tuned (bsk_autotune_batched)
+    or default launch shape."""
+    B = len(imgs)
+    if outs is None:
+        outs = [torch.empty_like(x) for x in imgs]
+    descs = _batch_descs(imgs, outs, radii, sigmas, Ns)
+    opt = _options(strip_h=strip_h, block=block, order_chunk=order_chunk)
     lib = _lib.load()
     with torch.cuda.device(imgs[0].device):
         if graph_key is None:
@@ -239,6 +248,58 @@ def bilateral_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas
             _lib.check(lib.bilateral_shiftable_batched_graph(descs, B, float(T), ctypes.byref(opt), int(graph_key),
                                                              _stream()))
     return outs
+
+
+def batched_shape(shapes: Sequence[Tuple[int, int]], radii: Sequence[int], sigmas: Sequence[float],
+                  T: float = 255.0, Ns: Optional[Sequence[int]] = None, strip_h: int = 0, block: int = 0,
+                  order_chunk: int = 0):
+    """The launch shape the batched entry points would use for images of these (H, W):
+    (lanes per workgroup, [rows per unit], [orders per pass]).  Host-side planning only:
+    the descriptors carry placeholder addresses that nothing reads."""
+    B = len(shapes)
+    descs = (_lib.ImageDesc * B)()
+    for b, (h, w) in enumerate(shapes):
+        # disjoint placeholder ranges, far apart, never dereferenced
+        descs[b].img = (2 * b + 1) << 36
+        descs[b].out = (2 * b + 2) << 36
+        descs[b].H, descs[b].W = int(h), int(w)
+        descs[b].radius = int(radii[b])
+        descs[b].sigma_r = float(sigmas[b])
+        descs[b].N = -1 if Ns is None or Ns[b] is None else int(Ns[b])
+    opt = _options(strip_h=strip_h, block=block, order_chunk=order_chunk)
+    blk = ctypes.c_int(0)
+    rows = (ctypes.c_int * B)()
+    chunk = (ctypes.c_int * B)()
+    _lib.check(_lib.load().bsk_batched_shape(descs, B, float(T), ctypes.byref(opt), ctypes.byref(blk), rows, chunk))
+    return blk.value, list(rows), list(chunk)
+
+
+def autotune_batched(imgs: Sequence[torch.Tensor], radii: Sequence[int], sigmas: Sequence[float], T: float = 255.0,
+                     Ns: Optional[Sequence[int]] = None, outs=None, path: Optional[str] = None):
+    """Times launch shapes of the batched kernel on these images, per (radius bucket, order
+    bucket), and stores the fastest for later batched calls; returns (block, ms)."""
+    if outs is None:
+        outs = [torch.empty_like(x) for x in imgs]
+    descs = _batch_descs(imgs, outs, radii, sigmas, Ns)
+    opt = _options()
+    blk, ms = ctypes.c_int(0), ctypes.c_double(0)
+    with torch.cuda.device(imgs[0].device):
+        _lib.check(_lib.load().bsk_autotune_batched(descs, len(imgs), float(T), ctypes.byref(opt),
+                                                    path.encode() if path else None, _stream(), ctypes.byref(blk),
+                                                    ctypes.byref(ms)))
+    return blk.value, ms.value
+
+
+def tune_cache_load(path: str):
+    _lib.check(_lib.load().bsk_tune_cache_load(path.encode()))
+
+
+def tune_cache_save(path: str):
+    _lib.check(_lib.load().bsk_tune_cache_save(path.encode()))
+
+
+def tune_cache_clear():
+    _lib.check(_lib.load().bsk_tune_cache_clear())
 
 
 def autotune(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None,

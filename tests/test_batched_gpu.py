@@ -78,3 +78,50 @@ def test_full_batch_256_images():
         idx = rng.integers(0, H * W, 400)
         ref = oracle.bilateral_at(f, idx, r, sg, order_for(sg, T))
         assert np.max(np.abs(outs[b].cpu().numpy().ravel()[idx] - ref)) <= 1e-4 * T
+
+
+def test_autotuned_shapes_are_applied(tmp_path):
+    """bsk_autotune_batched times the batch's launch shapes, stores the winners per
+    (radius bucket, order bucket) and writes them to its cache file; later batched
+    calls launch with exactly those shapes (as bsk_batched_shape reports) and still
+    match the single-image path with the same shape and the FP64 oracle."""
+    import json
+
+    from paper_1107_4617_amd import autotune_batched, batched_shape, tune_cache_clear
+
+    tune_cache_clear()
+    try:
+        specs, imgs = _batch(10, seed=43, lo=128, hi=400)
+        radii, sig = [s[2] for s in specs], [s[3] for s in specs]
+        path = tmp_path / "tune.jsonl"
+        block, ms = autotune_batched(imgs, radii, sig, T, path=str(path))
+        assert block in (256, 512, 1024) and ms > 0.0
+        entries = [json.loads(line) for line in path.read_text().splitlines()]
+        assert [e["block"] for e in entries if "batched_block_rb" in e] == [block]
+        tuned = {(e["batched_rb"], e["kb"]): (e["S"], e["kc"]) for e in entries
+                 if "batched_rb" in e and e["block"] == block}
+        blk, rows, chunk = batched_shape([tuple(x.shape) for x in imgs], radii, sig, T)
+        assert blk == block
+        for i, (H, W, r, sg, _) in enumerate(specs):
+            K = plan_K(sg)
+            key = (max(min(r, W - 1), min(r, H - 1)).bit_length(), (K - 1).bit_length())
+            if key in tuned:
+                assert rows[i] == min(tuned[key][0], H) and chunk[i] == tuned[key][1], (i, key)
+        outs = bilateral_batched(imgs, radii, sig, T)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(43)
+        for i, (H, W, r, sg, _) in enumerate(specs):
+            single = bilateral(imgs[i], r, sg, T, block=blk, strip_h=rows[i], order_chunk=chunk[i])
+            torch.cuda.synchronize()
+            assert float((single - outs[i]).abs().max()) <= 5e-4, i
+            if i % 3 == 0:
+                idx = rng.integers(0, H * W, 300)
+                ref = oracle.bilateral_at(imgs[i].cpu().numpy(), idx, r, sg, order_for(sg, T))
+                assert np.max(np.abs(outs[i].cpu().numpy().ravel()[idx] - ref)) <= 1e-4 * T
+    finally:
+        tune_cache_clear()
+
+
+def plan_K(sigma):
+    N = order_for(sigma, T)
+    return N // 2 + 1 if N % 2 == 0 else (N + 1) // 2
