@@ -231,6 +231,23 @@ int bilateral_shiftable_backward(const float *img, const float *grad_out, const 
                                  float T, const bsk_options *opt, float *grad_img,
                                  float *grad_sigma, void *stream);
 
+/*
+ * The training forward and the adjoint above for a stack of B images of one
+ * size, filtered with one set of parameters, each in ONE launch (the tiles of
+ * all images share the grid).  Layout, all dense and device-resident:
+ *   img, out, grad_out, grad_img: [B][H][W] floats
+ *   saved:                        [B][3][H][W] floats (Q, E1, E2 per image)
+ * Each image is filtered exactly as by the single-image call; grad_sigma
+ * receives the sum over the stack of dL/d sigma_r (sigma_r is shared, so this
+ * is the gradient of the summed loss), reduced in a fixed order.  B >= 1;
+ * other arguments and errors as for the single-image calls.
+ */
+int bilateral_shiftable_train_stack(const float *img, int B, int H, int W, int radius, float sigma_r, float T,
+                                    const bsk_options *opt, float *out, float *saved, void *stream);
+int bilateral_shiftable_backward_stack(const float *img, const float *grad_out, const float *out,
+                                       const float *saved, int B, int H, int W, int radius, float sigma_r, float T,
+                                       const bsk_options *opt, float *grad_img, float *grad_sigma, void *stream);
+
 /* One image of a batched call (FP32, device pointers, dense pitch). */
 typedef struct {
     const float *img;

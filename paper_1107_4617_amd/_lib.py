@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "BSK_OK", -1: "BSK_EINVAL", -2: "BSK_ERANGE", -3: "BSK_ENOMEM
 # Every symbol include/bsk.h declares.
 EXPORTS = [
     "bilateral_shiftable", "bilateral_shiftable_ex", "bilateral_shiftable_noalloc", "bilateral_shiftable_nlm2", "bilateral_shiftable_train",
-    "bilateral_shiftable_backward", "bilateral_shiftable_batched", "bilateral_shiftable_batched_graph",
+    "bilateral_shiftable_backward", "bilateral_shiftable_train_stack", "bilateral_shiftable_backward_stack",
+    "bilateral_shiftable_batched", "bilateral_shiftable_batched_graph",
     "bsk_order_for", "bsk_plan_info", "bsk_truncation_error", "bsk_poly_order_for", "bsk_poly_plan_info",
     "bsk_autotune", "bsk_batched_shape", "bsk_autotune_batched", "bsk_tune_cache_load", "bsk_tune_cache_save",
     "bsk_tune_cache_clear", "bsk_set_workspace_limit", "bsk_last_error", "bsk_release", "bsk_version",
@@ -82,6 +83,10 @@ def load():
         "bilateral_shiftable_train": (_i, [_vp, _i, _i, _i, _f, _f, ctypes.POINTER(Options), _vp, _vp, _vp]),
         "bilateral_shiftable_backward": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _f, _f, ctypes.POINTER(Options),
                                               _vp, _vp, _vp]),
+        "bilateral_shiftable_train_stack": (_i, [_vp, _i, _i, _i, _i, _f, _f, ctypes.POINTER(Options), _vp, _vp,
+                                                 _vp]),
+        "bilateral_shiftable_backward_stack": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _f, _f,
+                                                    ctypes.POINTER(Options), _vp, _vp, _vp]),
         "bilateral_shiftable_batched": (_i, [ctypes.POINTER(ImageDesc), _i, _f, ctypes.POINTER(Options), _vp]),
         "bilateral_shiftable_batched_graph": (_i, [ctypes.POINTER(ImageDesc), _i, _f, ctypes.POINTER(Options),
                                                    _i, _vp]),

@@ -204,7 +204,8 @@ static int kernel_occupancy(const Resolved &r, int kind)
     return occ;
 }
 
-int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r, int kind)
+int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r, int kind,
+            int nimg)
 {
     if (H < 1 || W < 1) return fail(BSK_EINVAL, "image size %dx%d must be positive", H, W);
     if (radius < 0) return fail(BSK_EINVAL, "radius %d must be >= 0", radius);
@@ -394,7 +395,7 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         // appears.
         const int bpc = kernel_occupancy(*r, kind);
         const long long target = 1LL * bpc * device_cus();
-        long long segs = target / strips;
+        long long segs = target / ((long long)strips * (nimg > 1 ? nimg : 1));
         if (segs < 1) segs = 1;
         int bestS = (int)((H + segs - 1) / segs);
         if (bestS < 8) bestS = 8;
@@ -735,21 +736,110 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
     return BSK_OK;
 }
 
-int train_impl(const float *img, int H, int W, const Resolved &r, float *out, float *saved, void *stream)
+// Training forward of B stacked images (B = 1: one image): img and out are
+// [B][H][W], saved is [B][3][H][W].
+int train_impl(const float *img, int B, int H, int W, const Resolved &r, float *out, float *saved, void *stream)
 {
     bsk::StripArgs a;
     fill_args(&a, r, H, W, r.kc);
     a.io.img = img;
     a.io.out = out;
     a.io.out2 = saved;
+    const long long plane = (long long)H * W * 4;
+    a.nimg = B;
+    a.bs_img = a.bs_out = plane;
+    a.bs_out2 = 3 * plane;
     if (r.plan.K > r.kc) {
         void *ws = nullptr;
-        int st = get_ws(stream, kWsTrainAcc, (size_t)bsk::acc_count_train() * H * W * 4, &ws);
+        int st = get_ws(stream, kWsTrainAcc, (size_t)bsk::acc_count_train() * plane * B, &ws);
         if (st) return st;
         a.ws = ws;
+        a.bs_ws = bsk::acc_count_train() * plane;
     }
     hipError_t e = bsk::launch_train_f32(a, r.block, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "train launch");
+    return BSK_OK;
+}
+
+int train_entry(const float *img, int B, int H, int W, int radius, float sigma_r, float T, const bsk_options *opt,
+                float *out, float *saved, void *stream)
+{
+    if (!img || !out || !saved) return fail(BSK_EINVAL, "null pointer");
+    if (B < 1) return fail(BSK_EINVAL, "need at least one image");
+    Resolved r;
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kTrain, B);
+    if (st) return st;
+    if (r.prec != BSK_FP32 || r.kahan)
+        return fail(BSK_EUNSUPPORTED, "the training forward is FP32 without compensation");
+    if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "training forward needs dense pitch");
+    const size_t n = (size_t)H * W * 4 * B;
+    if (overlap(img, n, out, n) || overlap(img, n, saved, 3 * n) || overlap(out, n, saved, 3 * n))
+        return fail(BSK_EINVAL, "buffers overlap");
+    return train_impl(img, B, H, W, r, out, saved, stream);
+}
+
+int backward_entry(const float *img, const float *grad_out, const float *out, const float *saved, int B, int H, int W,
+                   int radius, float sigma_r, float T, const bsk_options *opt, float *grad_img, float *grad_sigma,
+                   void *stream)
+{
+    if (!img || !grad_out) return fail(BSK_EINVAL, "null pointer");
+    if (B < 1) return fail(BSK_EINVAL, "need at least one image");
+    if ((out == nullptr) != (saved == nullptr)) return fail(BSK_EINVAL, "out and saved must both be given or both NULL");
+    Resolved r;
+    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kBackward, B);
+    if (st) return st;
+    if (r.prec != BSK_FP32 || r.kahan) return fail(BSK_EUNSUPPORTED, "the adjoint is FP32");
+    if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "the adjoint needs dense pitch");
+    const size_t n = (size_t)H * W * 4 * B;
+    if (grad_img && (overlap(grad_img, n, img, n) || overlap(grad_img, n, grad_out, n)))
+        return fail(BSK_EINVAL, "grad_img overlaps an input");
+    if (!grad_img && !grad_sigma) return BSK_OK;
+
+    const long long plane = (long long)H * W * 4;
+    if (!out) {
+        void *tmp = nullptr;
+        st = get_ws(stream, kWsBwdTrain, 4 * n, &tmp);
+        if (st) return st;
+        float *u = (float *)tmp;
+        float *sv = u + (size_t)H * W * B;
+        // the training forward with its own launch shape
+        Resolved rt;
+        st = resolve(H, W, radius, sigma_r, T, opt, &rt, kTrain, B);
+        if (st) return st;
+        st = train_impl(img, B, H, W, rt, u, sv, stream);
+        if (st) return st;
+        out = u;
+        saved = sv;
+    }
+    bsk::StripArgs a;
+    fill_args(&a, r, H, W, r.kc);
+    a.io.img = img;
+    a.io.aux0 = grad_out;
+    a.io.aux1 = saved;                      // Q
+    a.io.aux2 = out;                        // u
+    a.io.aux3 = saved + (size_t)H * W;      // E1
+    a.io.aux4 = saved + 2 * (size_t)H * W;  // E2
+    a.io.out = grad_img;
+    a.nimg = B;
+    a.bs_img = plane;
+    a.bs_out = grad_img ? plane : 0;
+    a.bs_aux[0] = a.bs_aux[2] = plane;
+    a.bs_aux[1] = a.bs_aux[3] = a.bs_aux[4] = 3 * plane;
+    const int nred = nblocks(r, H, W) * B;
+    void *red = nullptr;
+    st = get_ws(stream, kWsBwdRed, (size_t)nred * sizeof(double), &red);
+    if (st) return st;
+    a.red = (double *)red;
+    if (r.plan.K > r.kc) {
+        void *ws = nullptr;
+        st = get_ws(stream, kWsBwdAcc, (size_t)bsk::acc_count_backward() * plane * B, &ws);
+        if (st) return st;
+        a.ws = ws;
+        a.bs_ws = bsk::acc_count_backward() * plane;
+    }
+    hipError_t e = bsk::launch_backward_f32(a, r.block, r.kc, grad_sigma, 1.0 / (double)sigma_r, nred,
+                                            (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
     return BSK_OK;
 }
 
@@ -781,74 +871,29 @@ int bilateral_shiftable_nlm2(const float *img, int H, int W, int radius, float s
 int bilateral_shiftable_train(const float *img, int H, int W, int radius, float sigma_r, float T,
                               const bsk_options *opt, float *out, float *saved, void *stream)
 {
-    if (!img || !out || !saved) return fail(BSK_EINVAL, "null pointer");
-    Resolved r;
-    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kTrain);
-    if (st) return st;
-    if (r.prec != BSK_FP32 || r.kahan)
-        return fail(BSK_EUNSUPPORTED, "the training forward is FP32 without compensation");
-    if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "training forward needs dense pitch");
-    const size_t n = (size_t)H * W * 4;
-    if (overlap(img, n, out, n) || overlap(img, n, saved, 3 * n) || overlap(out, n, saved, 3 * n))
-        return fail(BSK_EINVAL, "buffers overlap");
-    return train_impl(img, H, W, r, out, saved, stream);
+    return train_entry(img, 1, H, W, radius, sigma_r, T, opt, out, saved, stream);
+}
+
+int bilateral_shiftable_train_stack(const float *img, int B, int H, int W, int radius, float sigma_r, float T,
+                                    const bsk_options *opt, float *out, float *saved, void *stream)
+{
+    return train_entry(img, B, H, W, radius, sigma_r, T, opt, out, saved, stream);
 }
 
 int bilateral_shiftable_backward(const float *img, const float *grad_out, const float *out, const float *saved,
                                  int H, int W, int radius, float sigma_r, float T, const bsk_options *opt,
                                  float *grad_img, float *grad_sigma, void *stream)
 {
-    if (!img || !grad_out) return fail(BSK_EINVAL, "null pointer");
-    if ((out == nullptr) != (saved == nullptr)) return fail(BSK_EINVAL, "out and saved must both be given or both NULL");
-    Resolved r;
-    int st = resolve(H, W, radius, sigma_r, T, opt, &r, kBackward);
-    if (st) return st;
-    if (r.prec != BSK_FP32 || r.kahan) return fail(BSK_EUNSUPPORTED, "the adjoint is FP32");
-    if (r.pitch_in != W || r.pitch_out != W) return fail(BSK_EUNSUPPORTED, "the adjoint needs dense pitch");
-    const size_t n = (size_t)H * W * 4;
-    if (grad_img && (overlap(grad_img, n, img, n) || overlap(grad_img, n, grad_out, n)))
-        return fail(BSK_EINVAL, "grad_img overlaps an input");
-    if (!grad_img && !grad_sigma) return BSK_OK;
+    return backward_entry(img, grad_out, out, saved, 1, H, W, radius, sigma_r, T, opt, grad_img, grad_sigma,
+                          stream);
+}
 
-    if (!out) {
-        void *tmp = nullptr;
-        st = get_ws(stream, kWsBwdTrain, 4 * n, &tmp);
-        if (st) return st;
-        float *u = (float *)tmp;
-        float *sv = u + (size_t)H * W;
-        // the training forward with its own launch shape
-        Resolved rt;
-        st = resolve(H, W, radius, sigma_r, T, opt, &rt, kTrain);
-        if (st) return st;
-        st = train_impl(img, H, W, rt, u, sv, stream);
-        if (st) return st;
-        out = u;
-        saved = sv;
-    }
-    bsk::StripArgs a;
-    fill_args(&a, r, H, W, r.kc);
-    a.io.img = img;
-    a.io.aux0 = grad_out;
-    a.io.aux1 = saved;                      // Q
-    a.io.aux2 = out;                        // u
-    a.io.aux3 = saved + (size_t)H * W;      // E1
-    a.io.aux4 = saved + 2 * (size_t)H * W;  // E2
-    a.io.out = grad_img;
-    const int nred = nblocks(r, H, W);
-    void *red = nullptr;
-    st = get_ws(stream, kWsBwdRed, (size_t)nred * sizeof(double), &red);
-    if (st) return st;
-    a.red = (double *)red;
-    if (r.plan.K > r.kc) {
-        void *ws = nullptr;
-        st = get_ws(stream, kWsBwdAcc, (size_t)bsk::acc_count_backward() * H * W * 4, &ws);
-        if (st) return st;
-        a.ws = ws;
-    }
-    hipError_t e = bsk::launch_backward_f32(a, r.block, r.kc, grad_sigma, 1.0 / (double)sigma_r, nred,
-                                            (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "backward launch");
-    return BSK_OK;
+int bilateral_shiftable_backward_stack(const float *img, const float *grad_out, const float *out,
+                                       const float *saved, int B, int H, int W, int radius, float sigma_r, float T,
+                                       const bsk_options *opt, float *grad_img, float *grad_sigma, void *stream)
+{
+    return backward_entry(img, grad_out, out, saved, B, H, W, radius, sigma_r, T, opt, grad_img, grad_sigma,
+                          stream);
 }
 
 int bsk_order_for(float sigma_r, float T)

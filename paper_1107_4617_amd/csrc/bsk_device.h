@@ -168,16 +168,19 @@ __device__ __forceinline__ double quant(double x) { return x; }
 template <typename AT>
 struct Chain {
     AT c, s, cp, sp, a2;   // current, previous, 2 cos(delta g)
+    // M >= 0: the start mode is that compile-time constant (one-pass launches);
+    // M < 0: the run-time `mode`, resolved with selects (a branch per mode
+    // measured slower there).
+    template <int M = -1>
     __device__ __forceinline__ void start(bool valid, AT g, AT om0, AT dlt, int mode)
     {
-        if (mode <= 1) {
-            // the half step angle y = delta g / 2 (= omega_0 g when omega_0 = delta / 2),
-            // then the step by the double-angle formulas
+        if constexpr (M == 0 || M == 1) {
+            // the half step angle y = delta g / 2, then the step by the double-angle formulas
             AT sh, ch;
             sc_small(AT(0.5) * dlt * g, &sh, &ch);
             const AT cd = fmat(AT(-2) * sh, sh, AT(1));
             a2 = AT(2) * cd;
-            if (mode == 0) {
+            if constexpr (M == 0) {
                 // omega_0 = 0: (c, s) = (1, 0) and the order before it at -delta g
                 const AT sd = AT(2) * sh * ch;
                 c = valid ? AT(1) : AT(0);
@@ -185,23 +188,34 @@ struct Chain {
                 cp = valid ? cd : AT(0);
                 sp = valid ? -sd : AT(0);
             } else {
-                // omega_0 = delta / 2: (c, s) = (ch, sh) and the order before it at -y
+                // omega_0 = delta / 2 = y / g: (c, s) = (ch, sh) and the order before it at -y
                 c = valid ? ch : AT(0);
                 s = valid ? sh : AT(0);
                 cp = c;
                 sp = -s;
             }
-            return;
+        } else {
+            AT c0, s0, cd, sd;
+            if (mode <= 1) {
+                // the half step angle y = delta g / 2 (= omega_0 g when omega_0 = delta / 2),
+                // then the step by the double-angle formulas
+                AT sh, ch;
+                sc_small(AT(0.5) * dlt * g, &sh, &ch);
+                cd = fmat(AT(-2) * sh, sh, AT(1));
+                sd = AT(2) * sh * ch;
+                c0 = mode == 0 ? AT(1) : ch;
+                s0 = mode == 0 ? AT(0) : sh;
+            } else {
+                sc(om0 * g, &s0, &c0);
+                sc_step(dlt * g, &sd, &cd);
+            }
+            const AT z = valid ? AT(1) : AT(0);
+            c = z * c0;
+            s = z * s0;
+            cp = z * (c0 * cd + s0 * sd);   // (cos, sin) of (omega_0 - delta) g
+            sp = z * (s0 * cd - c0 * sd);
+            a2 = AT(2) * cd;
         }
-        AT c0, s0, cd, sd;
-        sc(om0 * g, &s0, &c0);
-        sc_step(dlt * g, &sd, &cd);
-        const AT z = valid ? AT(1) : AT(0);
-        c = z * c0;
-        s = z * s0;
-        cp = z * (c0 * cd + s0 * sd);   // (cos, sin) of (omega_0 - delta) g
-        sp = z * (s0 * cd - c0 * sd);
-        a2 = AT(2) * cd;
     }
     // S0: the current sine value is exactly zero (the zero frequency), so the
     // next one is -sp without a multiply-add on the zero
@@ -427,7 +441,7 @@ __device__ __forceinline__ void chain_start(CH &ch, bool valid, const AT *aux, A
         else
             ch.start(valid, AT(1), fmat(om1, aux[0], om0 * aux[1]), dlt * aux[1], 2);
     } else {
-        ch.start(valid, aux[0], om0, dlt, mode);
+        ch.template start<POL::START>(valid, aux[0], om0, dlt, mode);
     }
 }
 

@@ -55,8 +55,10 @@ struct Resolved {
 // The kernel family a request is resolved for: its pass sizes and residency
 // set the orders per pass and the segment height.
 enum Kind { kForward = 0, kTrain = 1, kBackward = 2, kPatch2 = 3 };
+// nimg: the images of one size launched together (they share the round of
+// resident workgroups the segment height is chosen for).
 int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r,
-            int kind = kForward);
+            int kind = kForward, int nimg = 1);
 // Orders per pass from a kernel family's full pass and a smaller one (0: half
 // the full one): the one with the lower estimated cost for K orders.
 int pick_chunk(int K, int full, int small = 0);

@@ -137,7 +137,21 @@ struct StripArgs {
     int p2_group;
     double p2_omega1_base, p2_delta1;
     const float *vf_dev;
+    // A stack of nimg images of one size and one set of parameters in one launch
+    // (0 or 1: a single image).  Image b's buffers start b times the byte stride
+    // of each buffer after image 0's: the input, main output, saved planes, the
+    // five auxiliary inputs, and the workspace (zero for a null buffer, which
+    // stays null).  The tiles of all images share one grid; partial sums in
+    // `red` are indexed by the tile over the stack.
+    int nimg;
+    long long bs_img, bs_out, bs_out2, bs_aux[5], bs_ws;
 };
+
+// Tiles of a strip launch: strips x segments per image x images.
+inline long long strip_tiles(const StripArgs &a)
+{
+    return (long long)a.strips * ((a.io.H + a.S - 1) / a.S) * (a.nimg > 1 ? a.nimg : 1);
+}
 
 // Per-launch arguments of the polynomial-kernel strip kernel.
 struct PolyArgs {

@@ -63,15 +63,62 @@ __device__ __forceinline__ Geom geom_of(const StripArgs &a)
     return gm;
 }
 
+// Tile of the launch's grid over a stack of images: its strip bx, the image b
+// it lies in and its segment by within that image.  Returns false for the
+// workgroups past the last tile.
+__device__ __forceinline__ bool stack_tile(const StripArgs &a, int *bx, int *by, int *b)
+{
+    const int segs = (a.io.H + a.S - 1) / a.S;
+    const int nimg = a.nimg > 1 ? a.nimg : 1;
+    if (!xcd_tile(a.strips, segs * nimg, bx, by)) return false;
+    *b = *by / segs;
+    *by -= *b * segs;
+    return true;
+}
+// Image b's buffers (a null buffer has a zero stride and stays null).
+template <typename P>
+__device__ __forceinline__ P at_image(P p, int b, long long bs)
+{
+    return (P)((const char *)p + b * bs);
+}
+__device__ __forceinline__ IO stack_io(const StripArgs &a, int b)
+{
+    IO io = a.io;
+    io.img = at_image(io.img, b, a.bs_img);
+    io.out = at_image(io.out, b, a.bs_out);
+    io.out2 = at_image(io.out2, b, a.bs_out2);
+    io.aux0 = at_image(io.aux0, b, a.bs_aux[0]);
+    io.aux1 = at_image(io.aux1, b, a.bs_aux[1]);
+    io.aux2 = at_image(io.aux2, b, a.bs_aux[2]);
+    io.aux3 = at_image(io.aux3, b, a.bs_aux[3]);
+    io.aux4 = at_image(io.aux4, b, a.bs_aux[4]);
+    return io;
+}
+__device__ __forceinline__ Geom stack_geom(const StripArgs &a, int b)
+{
+    Geom gm = geom_of(a);
+    gm.ws = at_image(gm.ws, b, a.bs_ws);
+    return gm;
+}
+
 template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int MINB = 0>
 __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, KL, BLOCK, AT>()))
     strip_kernel(const StripArgs a)
 {
     __shared__ __align__(16) AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
     int bx, by;
-    if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
-    const Geom gm = geom_of(a);
-    strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, bx, by, lds, nullptr, nullptr);
+    if constexpr (std::is_same<POL, PolTrain>::value) {
+        // the training forward also runs over image stacks
+        int b;
+        if (!stack_tile(a, &bx, &by, &b)) return;
+        const IO io = stack_io(a, b);
+        const Geom gm = stack_geom(a, b);
+        strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(io, gm, bx, by, lds, nullptr, nullptr);
+    } else {
+        if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
+        const Geom gm = geom_of(a);
+        strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(a.io, gm, bx, by, lds, nullptr, nullptr);
+    }
 }
 
 // FP32 forward with the separable spatial kernel (NSC non-zero frequencies,
@@ -113,11 +160,14 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward
 {
     __shared__ __align__(16) float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
     __shared__ double red_lds[BLOCK];
-    int bx, by;
-    if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
-    const Geom gm = geom_of(a);
-    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(a.io, gm, bx, by, lds, red_lds,
-                                                            a.red + ((long)by * a.strips + bx));
+    int bx, by, b;
+    if (!stack_tile(a, &bx, &by, &b)) return;
+    const IO io = stack_io(a, b);
+    const Geom gm = stack_geom(a, b);
+    // one partial sum per tile of the whole stack, image-major like the tiles
+    const long segs = (a.io.H + a.S - 1) / a.S;
+    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(io, gm, bx, by, lds, red_lds,
+                                                            a.red + (((long)b * segs + by) * a.strips + bx));
 }
 
 // Fixed-order sum of the per-workgroup partials: grad_sigma = -(1/sigma) sum.
@@ -154,7 +204,7 @@ static hipError_t launch(const StripArgs &a, hipStream_t s, int *occ)
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
-    const dim3 grid(xcd_grid(a.strips, (a.io.H + a.S - 1) / a.S));
+    const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
     hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -289,7 +339,7 @@ static hipError_t bwd(const StripArgs &a, hipStream_t s, int *occ)
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
-    const dim3 grid(xcd_grid(a.strips, (a.io.H + a.S - 1) / a.S));
+    const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
     hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -328,7 +378,7 @@ static hipError_t spatial_launch(const StripArgs &a, hipStream_t s, int *occ)
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
-    const dim3 grid(xcd_grid(a.strips, (a.io.H + a.S - 1) / a.S));
+    const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
     hipLaunchKernelGGL((spatial_kernel<BLOCK, KR, NSC, SEVEN>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }

@@ -24,13 +24,14 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _check_image(t: torch.Tensor, name: str, dtype=torch.float32):
+def _check_image(t: torch.Tensor, name: str, dtype=torch.float32, stack: bool = False):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if not t.is_cuda:
         raise TypeError(f"{name} must be a GPU tensor (libbsk runs only on the GPU)")
-    if t.dim() != 2:
-        raise ValueError(f"{name} must be 2-D (H, W), got shape {tuple(t.shape)}")
+    if t.dim() != 2 and not (stack and t.dim() == 3):
+        want = "2-D (H, W) or 3-D (B, H, W)" if stack else "2-D (H, W)"
+        raise ValueError(f"{name} must be {want}, got shape {tuple(t.shape)}")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
@@ -174,40 +175,64 @@ def spatial_sigma_for(T_s: float, Ns: int) -> float:
 
 
 def bilateral_train(img: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0, N: Optional[int] = None):
-    """(out, saved) where saved is (3, H, W): Q, E1, E2 for the adjoint."""
-    _check_image(img, "img")
-    H, W = img.shape
+    """(out, saved): the filter output and the planes the adjoint needs, saved = (Q, E1, E2).
+
+    img (H, W) gives saved of shape (3, H, W); a stack (B, H, W) of images filtered with the
+    same parameters runs as one launch and gives saved of shape (B, 3, H, W)."""
+    _check_image(img, "img", stack=True)
+    H, W = img.shape[-2:]
+    B = img.shape[0] if img.dim() == 3 else 1
     out = torch.empty_like(img)
-    saved = torch.empty((3, H, W), dtype=torch.float32, device=img.device)
+    saved = torch.empty((*img.shape[:-2], 3, H, W), dtype=torch.float32, device=img.device)
     opt = _options(N)
+    lib = _lib.load()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     with torch.cuda.device(img.device):
-        _lib.check(_lib.load().bilateral_shiftable_train(
-            ctypes.c_void_p(img.data_ptr()), H, W, int(radius), float(sigma_r), float(T), ctypes.byref(opt),
-            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(saved.data_ptr()), _stream()))
+        if img.dim() == 2:
+            _lib.check(lib.bilateral_shiftable_train(p(img), H, W, int(radius), float(sigma_r), float(T),
+                                                     ctypes.byref(opt), p(out), p(saved), _stream()))
+        else:
+            _lib.check(lib.bilateral_shiftable_train_stack(p(img), B, H, W, int(radius), float(sigma_r), float(T),
+                                                           ctypes.byref(opt), p(out), p(saved), _stream()))
     return out, saved
 
 
 def bilateral_backward(img: torch.Tensor, grad_out: torch.Tensor, radius: int, sigma_r: float, T: float = 255.0,
                        N: Optional[int] = None, out: Optional[torch.Tensor] = None,
                        saved: Optional[torch.Tensor] = None, need_img: bool = True, need_sigma: bool = True):
-    """(dL/dimg or None, dL/dsigma_r as a 0-d tensor or None)."""
-    _check_image(img, "img")
-    _check_image(grad_out, "grad_out")
-    H, W = img.shape
+    """(dL/dimg or None, dL/dsigma_r as a 0-d tensor or None).
+
+    For a stack img (B, H, W) (one launch), dL/dsigma_r is summed over the stack."""
+    _check_image(img, "img", stack=True)
+    _check_image(grad_out, "grad_out", stack=True)
+    if grad_out.shape != img.shape:
+        raise ValueError("grad_out must have the shape of img")
+    H, W = img.shape[-2:]
+    B = img.shape[0] if img.dim() == 3 else 1
     if (out is None) != (saved is None):
         raise ValueError("give both out and saved, or neither")
     if out is not None:
-        _check_image(out, "out")
-        if saved.shape != (3, H, W) or not saved.is_contiguous() or saved.dtype != torch.float32:
-            raise ValueError("saved must be a contiguous float32 (3, H, W) tensor")
+        _check_image(out, "out", stack=True)
+        if out.shape != img.shape:
+            raise ValueError("out must have the shape of img")
+        if (saved.shape != (*img.shape[:-2], 3, H, W) or not saved.is_contiguous()
+                or saved.dtype != torch.float32):
+            raise ValueError("saved must be a contiguous float32 tensor of shape (3, H, W), or (B, 3, H, W) "
+                             "for a stack")
     gi = torch.empty_like(img) if need_img else None
     gs = torch.empty((), dtype=torch.float32, device=img.device) if need_sigma else None
     opt = _options(N)
     p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+    lib = _lib.load()
     with torch.cuda.device(img.device):
-        _lib.check(_lib.load().bilateral_shiftable_backward(
-            p(img), p(grad_out), p(out), p(saved), H, W, int(radius), float(sigma_r), float(T),
-            ctypes.byref(opt), p(gi), p(gs), _stream()))
+        if img.dim() == 2:
+            _lib.check(lib.bilateral_shiftable_backward(
+                p(img), p(grad_out), p(out), p(saved), H, W, int(radius), float(sigma_r), float(T),
+                ctypes.byref(opt), p(gi), p(gs), _stream()))
+        else:
+            _lib.check(lib.bilateral_shiftable_backward_stack(
+                p(img), p(grad_out), p(out), p(saved), B, H, W, int(radius), float(sigma_r), float(T),
+                ctypes.byref(opt), p(gi), p(gs), _stream()))
     return gi, gs
 
 
@@ -360,7 +385,9 @@ class ShiftableBilateral(torch.nn.Module):
         self.sigma_r = torch.nn.Parameter(torch.tensor(float(sigma_r)))
 
     def forward(self, img: torch.Tensor) -> torch.Tensor:
+        """img (H, W), or (..., H, W): the leading dimensions form one stack, filtered by one
+        training-forward launch (and one adjoint launch in the backward pass)."""
         if img.dim() == 2:
             return BilateralFunction.apply(img, self.sigma_r, self.radius, self.T, self.N)
-        return torch.stack([BilateralFunction.apply(x, self.sigma_r, self.radius, self.T, self.N)
-                            for x in img.reshape(-1, *img.shape[-2:])]).reshape(img.shape)
+        x = img.reshape(-1, *img.shape[-2:]).contiguous()
+        return BilateralFunction.apply(x, self.sigma_r, self.radius, self.T, self.N).reshape(img.shape)
