@@ -37,11 +37,16 @@ PEAK_HBM_GBS = 8000.0         # MI355X HBM3E
 # running-sum updates 16, recombination of P and Q 10.
 FLOP_PER_PX_ORDER = 34
 BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
-# HBM bytes per launch of the headline kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a 256 MiB copy (profiles/strip_kernel_fwd_rect4096_r20_s30.md).
-# Valid for this kernel build only: set to None when the kernel changes.
+# HBM bytes and VALU wave-instructions per launch of the headline kernel, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy) and
+# SQ_INSTS_VALU (profiles/strip_kernel_fwd_rect4096_r20_s30.md).  Valid for this
+# kernel build only: set to None when the kernel changes.
 HEADLINE_KERNEL = "strip_kernel<float,256,16,4,PolForward<float,0>,0,false,3>"
-HEADLINE_HBM_BYTES = 283.0e6
+HEADLINE_HBM_BYTES = 283.3e6
+HEADLINE_VALU_INSTS = 212.17e6
+# VALU issue: one wave64 instruction per SIMD every 4 cycles (16 lanes, no
+# packed FP32), 4 SIMDs per CU, 256 CUs at 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 METRIC = "Mpixel/s + %HBM roofline, 4096\u00b2 r=20 \u03c3r=30; fwd+bwd and BF16 vs plain FP32"
 
 
@@ -94,6 +99,91 @@ def cpu_baseline(img, radius, sigma, N, T, gpu_out=None, budget_s=20.0):
     return base, parity
 
 
+class OracleErrors:
+    """Errors of GPU outputs against the FP64 oracle, evaluated in the CPU-baseline leg.
+
+    sample() picks, while the GPU output still exists, n seeded random pixels plus, when
+    worst_vs (another output of the same workload, e.g. the plain FP32 one) is given, the
+    `worst` pixels where the output departs most from it, and keeps the output's values
+    there; evaluate() later runs the oracle at those pixels (ref_at(idx): the oracle
+    at flat pixel indices) and writes the errors into the result dictionaries."""
+
+    def __init__(self):
+        self.pending = []
+
+    def sample(self, into, out, ref_at, tol, n=100_000, seed=321, worst_vs=None, worst=2000):
+        import torch
+        flat = out.detach().double().ravel()
+        idx = np.random.default_rng(seed).integers(0, flat.numel(), n)
+        if worst_vs is not None:
+            d = (out.double() - worst_vs.double()).abs().ravel()
+            top = torch.topk(d, min(worst, d.numel())).indices.cpu().numpy()
+            idx = np.concatenate([idx, top])
+        idx = np.unique(idx)
+        vals = flat[torch.from_numpy(idx).to(flat.device)].cpu().numpy()
+        self.pending.append((into, vals, idx, ref_at, tol))
+
+    def evaluate(self):
+        for into, vals, idx, ref_at, tol in self.pending:
+            err = np.abs(vals - ref_at(idx))
+            m = float(err.max())
+            e = {"vs": "oracle", "pixels": int(idx.size), "max_abs": m, "rms": float(np.sqrt(np.mean(err ** 2))),
+                 "p99.99": float(np.quantile(err, 0.9999)), "tolerance": tol, "within": bool(m <= tol)}
+            if "error" in into and isinstance(into["error"], list):
+                into["error"].append(e)
+            else:
+                into["error"] = e
+        self.pending = []
+
+
+def _oracle():
+    import oracle
+    return oracle
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
+def copy_bandwidth(dev, mib=1024, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a plain torch copy."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
+
+
+def child_processes():
+    """Processes this one has started that still exist (the benchmark starts none; the
+    oracle's OpenMP workers are threads)."""
+    try:
+        import psutil
+        return [f"{c.pid}:{c.name()}" for c in psutil.Process().children(recursive=True)]
+    except Exception as e:  # noqa: BLE001
+        return [f"unknown ({type(e).__name__})"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,9 +207,11 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1107_4617_amd import (bilateral, bilateral_backward, bilateral_batched, bilateral_train,
-                                     nlm2, plan_info, poly_order_for, poly_plan_info, spatial_filter,
-                                     spatial_sigma_for)
+
+    from paper_1107_4617_amd import (autotune_batched, batched_shape, bilateral, bilateral_backward,
+                                     bilateral_batched, bilateral_train, nlm2, order_for, plan_info,
+                                     poly_order_for, poly_plan_info, spatial_filter, spatial_sigma_for,
+                                     tune_cache_clear)
     from paper_1107_4617_amd import workloads as wl
 
     dev = torch.device("cuda:0")
@@ -228,6 +320,22 @@ def main():
         },
         "median_ms": round(med_ms, 4),
     }
+    log("timing a 1 GiB device copy")
+    copy_gbs = copy_bandwidth(dev)
+    rl = rec["roofline"]
+    rl["copy_GB/s"] = round(copy_gbs, 1)
+    rl["hbm_frac_vs_copy"] = round(BYTES_PER_PX * px / (mean_ms * 1e-3) / 1e9 / copy_gbs, 4)
+    if HEADLINE_VALU_INSTS is not None:
+        # share of the launch during which the SIMDs issue VALU instructions
+        rl["valu_busy"] = round(HEADLINE_VALU_INSTS / VALU_ISSUE_PER_S / (mean_ms * 1e-3), 4)
+        rl["valu_lane_instructions_per_pixel_order"] = round(HEADLINE_VALU_INSTS * 64 / (px * K), 2)
+    else:
+        rl["valu_busy"] = None
+    # Errors of each variant below against the FP64 oracle, evaluated in the CPU-baseline leg:
+    # 100,000 seeded random pixels plus the 2,000 where the variant departs most from the
+    # plain FP32 output.
+    oe = OracleErrors()
+    at_head = lambda idx: _oracle().bilateral_at(img_np, idx, radius, sigma, N)  # noqa: E731
 
     if not args.no_extra:
         variants = {}
@@ -245,6 +353,15 @@ def main():
                 variants[name] = {"Mpixel/s": round(px / ms_q / 1e3, 2), "ms": round(ms_q, 4),
                                   "folded_orders": kb, "dropped_weight": eps,
                                   "max_abs_vs_fp32": float((outq - out).abs().max())}
+                oe.sample(variants[name], outq, at_head, 2e-3 * T, worst_vs=out)
+        # plain FP32 with the same truncation: the precision forms' order count in FP32
+        log("timing fp32 with weights below 1e-7 dropped")
+        ms_t, _, _ = time_calls(lambda: bilateral(img, radius, sigma, T, N=N, weight_eps=1e-7, out=outq),
+                                args.steps, args.warmup, stream)
+        variants["fp32_trunc1e-7"] = {"Mpixel/s": round(px / ms_t / 1e3, 2), "ms": round(ms_t, 4),
+                                      "folded_orders": kb, "dropped_weight": eps,
+                                      "max_abs_vs_fp32": float((outq - out).abs().max())}
+        oe.sample(variants["fp32_trunc1e-7"], outq, at_head, 1e-4 * T, worst_vs=out)
         del outq
         # FP64 throughout (transforms, sums, recombination) at the headline workload
         log("timing fp64 form")
@@ -257,42 +374,57 @@ def main():
                                              "fp64_frac": round(px * K * FLOP_PER_PX_ORDER / (ms_d * 1e-3) / 1e12
                                                                 / PEAK_FP64_TFLOPS, 4),
                                              "max_abs_vs_fp32": float((out64.float() - out).abs().max())}
+        oe.sample(variants["fp64_rect4096_r20_s30"], out64, at_head, 1e-9 * T, worst_vs=out)
         del img64, out64
         # Algorithm 2 with the separable q_2 spatial kernel (M = 9) and Algorithm 1 at the
         # headline size and window
         log("timing spatial kernels")
-        ms_sp, _, _ = time_calls(fwd_sp, args.steps, args.warmup, stream)
-        ms_a1, _, _ = time_calls(lambda: spatial_filter(img, radius, sig_s, 2, out=out), args.steps, args.warmup,
+        outv = torch.empty_like(img)
+        ms_sp, _, _ = time_calls(lambda: bilateral(img, radius, sigma, T, N=N, out=outv, spatial_sigma=sig_s,
+                                                   spatial_N=2), args.steps, args.warmup, stream)
+        v = variants["spatial_q2_M9_rect4096_r20_s30"] = {
+            "Mpixel/s": round(px / ms_sp / 1e3, 2), "ms": round(ms_sp, 4), "spatial_sigma": sig_s, "spatial_N": 2,
+            "vs_box": round(mean_ms / ms_sp, 3)}
+        oe.sample(v, outv, lambda idx: _oracle().bilateral_sp_at(img_np, idx, radius, sigma, N, sig_s, 2), 1e-4 * T)
+        ms_a1, _, _ = time_calls(lambda: spatial_filter(img, radius, sig_s, 2, out=outv), args.steps, args.warmup,
                                  stream)
-        variants["spatial_q2_M9_rect4096_r20_s30"] = {"Mpixel/s": round(px / ms_sp / 1e3, 2), "ms": round(ms_sp, 4),
-                                                      "spatial_sigma": sig_s, "spatial_N": 2,
-                                                      "vs_box": round(mean_ms / ms_sp, 3)}
-        variants["algorithm1_q2_rect4096_r20"] = {"Mpixel/s": round(px / ms_a1 / 1e3, 2), "ms": round(ms_a1, 4)}
+        v = variants["algorithm1_q2_rect4096_r20"] = {"Mpixel/s": round(px / ms_a1 / 1e3, 2), "ms": round(ms_a1, 4)}
+        oe.sample(v, outv, lambda idx: _oracle().bilateral_sp_at(img_np, idx, radius, 1.0, 0, sig_s, 2), 1e-4 * T)
         log("timing two-pixel-patch non-local means")
-        ms_nl, _, _ = time_calls(fwd_nlm, max(5, args.steps // 5), max(2, args.warmup // 5), stream)
-        ms_b60, _, _ = time_calls(lambda: bilateral(img, radius, 60.0, T, out=out), args.steps, args.warmup, stream)
-        variants["nlm2_patch_u01_s60_rect4096_r20"] = {"Mpixel/s": round(px / ms_nl / 1e3, 2), "ms": round(ms_nl, 4),
-                                                       "terms": 45, "bilateral_s60_ms": round(ms_b60, 4)}
+        ms_nl, _, _ = time_calls(lambda: nlm2(img, radius, 60.0, 60.0, (0, 1), T, out=outv),
+                                 max(5, args.steps // 5), max(2, args.warmup // 5), stream)
+        n60 = order_for(60.0, T)
+        v = variants["nlm2_patch_u01_s60_rect4096_r20"] = {"Mpixel/s": round(px / ms_nl / 1e3, 2),
+                                                           "ms": round(ms_nl, 4), "terms": 45}
+        oe.sample(v, outv, lambda idx: _oracle().nlm2_at(img_np, idx, radius, 60.0, n60, 60.0, n60, (0, 1)), 1e-4 * T)
+        ms_b60, _, _ = time_calls(lambda: bilateral(img, radius, 60.0, T, out=outv), args.steps, args.warmup, stream)
+        v["bilateral_s60_ms"] = round(ms_b60, 4)
         log("timing polynomial range kernel")
         n_p = poly_order_for(sigma, T)
-        for name, fn, eps_p in (("poly_pN37_rect4096_r20_s30", fwd_poly, 0.0),
-                                ("poly_pN37_trunc1e-7_rect4096_r20_s30", fwd_poly_t, 1e-7)):
-            ms_pl, _, _ = time_calls(fn, args.steps, args.warmup, stream)
+        at_poly = lambda idx: _oracle().bilateral_poly_at(img_np, idx, radius, sigma, n_p)  # noqa: E731
+        for name, eps_p in (("poly_pN37_rect4096_r20_s30", 0.0), ("poly_pN37_trunc1e-7_rect4096_r20_s30", 1e-7)):
+            ms_pl, _, _ = time_calls(lambda: bilateral(img, radius, sigma, T, out=outv, range_kernel="poly",
+                                                       weight_eps=eps_p), args.steps, args.warmup, stream)
             kp, bp = poly_plan_info(sigma, T, eps=eps_p)
             variants[name] = {"Mpixel/s": round(px / ms_pl / 1e3, 2), "ms": round(ms_pl, 4), "N": n_p,
                               "chebyshev_coefficients": kp, "dropped_bound": bp,
                               "vs_raised_cosine": round(mean_ms / ms_pl, 3)}
+            oe.sample(variants[name], outv, at_poly, 1e-4 * T)
         # the paper's timed instance: 512x512, T = 5 (11x11 window), M x N = 3^2 x 5, i.e. the
         # spatial q_2 on [-5, 5] and the range q_4 on [-255, 255] (sigma_r = 255 / pi)
-        small = torch.from_numpy(wl.smooth_image(512, 512, seed=1)).to(dev)
+        small_np = wl.smooth_image(512, 512, seed=1)
+        small = torch.from_numpy(small_np).to(dev)
         outs_ = torch.empty_like(small)
+        ss5 = spatial_sigma_for(5, 2)
         ms_p, _, _ = time_calls(lambda: bilateral(small, 5, T / math.pi, T, N=4, out=outs_,
-                                                  spatial_sigma=spatial_sigma_for(5, 2), spatial_N=2),
+                                                  spatial_sigma=ss5, spatial_N=2),
                                 args.steps, args.warmup, stream)
-        variants["paper_instance_512_T5_M9_N5"] = {"ms": round(ms_p, 4),
-                                                   "Mpixel/s": round(512 * 512 / ms_p / 1e3, 2),
-                                                   "paper_matlab_s": 2.5}
-        del small, outs_
+        v = variants["paper_instance_512_T5_M9_N5"] = {"ms": round(ms_p, 4),
+                                                       "Mpixel/s": round(512 * 512 / ms_p / 1e3, 2),
+                                                       "paper_matlab_s": 2.5}
+        oe.sample(v, outs_, lambda idx: _oracle().bilateral_sp_at(small_np, idx, 5, T / math.pi, 4, ss5, 2),
+                  1e-4 * T, n=512 * 512)
+        del small, outs_, outv
         # training forward + adjoint at the headline workload
         g = torch.randn_like(img)
 
@@ -302,61 +434,111 @@ def main():
 
         log("timing forward+backward")
         ms_fb, _, _ = time_calls(fb, max(3, args.steps // 2), 1, stream)
-        variants["fwd_bwd_fp32"] = {"Mpixel/s": round(px / ms_fb / 1e3, 2), "ms": round(ms_fb, 4)}
-        del g
-        # 8192^2, r=32, sigma_r=15, N=117: plain FP32 (59 orders) vs 16-bit stack + truncation (28 orders)
+        o_tr, _ = bilateral_train(img, radius, sigma, T, N)
+        v = variants["fwd_bwd_fp32"] = {"Mpixel/s": round(px / ms_fb / 1e3, 2), "ms": round(ms_fb, 4),
+                                        "error_note": "the training forward's output; the gradients are compared "
+                                                      "with the oracle's in the GPU tests"}
+        oe.sample(v, o_tr, at_head, 1e-4 * T)
+        del g, o_tr
+        # 8192^2, r=32, sigma_r=15, N=117: plain FP32 (59 orders) vs truncation at 1e-7 (28 orders)
+        # in FP32 and in the 16-bit stacks
         log("timing 8192^2 r=32 workload")
-        big = torch.from_numpy(wl.rect_image(8192, 8192, seed=3)).to(dev)
+        big_np = wl.rect_image(8192, 8192, seed=3)
+        big = torch.from_numpy(big_np).to(dev)
         outb = torch.empty_like(big)
-        ms_p, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, out=outb), 3, 1, stream)
-        ms_i, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, precision="i16", weight_eps=1e-7,
-                                                  kahan=True, out=outb), 3, 1, stream)
-        ms_n, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, precision="i16", weight_eps=1e-7,
-                                                  out=outb), 3, 1, stream)
+        out8 = torch.empty_like(big)
+        at8 = lambda idx: _oracle().bilateral_at(big_np, idx, 32, 15.0, 117)  # noqa: E731
         px8 = 8192 * 8192
-        variants["rect8192_r32_s15"] = {"fp32_Mpixel/s": round(px8 / ms_p / 1e3, 2),
-                                        "fp32_ms": round(ms_p, 3), "fp32_orders": plan_info(117, 0.0)[0],
-                                        "i16_kahan_trunc_Mpixel/s": round(px8 / ms_i / 1e3, 2),
-                                        "i16_kahan_trunc_ms": round(ms_i, 3),
-                                        "i16_trunc_Mpixel/s": round(px8 / ms_n / 1e3, 2),
-                                        "i16_trunc_ms": round(ms_n, 3), "i16_orders": plan_info(117, 1e-7)[0]}
-        del big, outb
+        ms_p, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, out=out8), 3, 1, stream)
+        v8 = {"fp32": {"Mpixel/s": round(px8 / ms_p / 1e3, 2), "ms": round(ms_p, 3),
+                       "orders": plan_info(117, 0.0)[0]}}
+        oe.sample(v8["fp32"], out8, at8, 1e-4 * T, n=20_000)
+        for name, kw in (("fp32_trunc", {}), ("i16_trunc", {"precision": "i16"}),
+                         ("i16_kahan_trunc", {"precision": "i16", "kahan": True}),
+                         ("fp16_trunc", {"precision": "fp16"}), ("bf16_trunc", {"precision": "bf16"})):
+            log(f"timing 8192^2 {name}")
+            ms_v, _, _ = time_calls(lambda: bilateral(big, 32, 15.0, T, N=117, weight_eps=1e-7, out=outb, **kw),
+                                    3, 1, stream)
+            v8[name] = {"Mpixel/s": round(px8 / ms_v / 1e3, 2), "ms": round(ms_v, 3),
+                        "orders": plan_info(117, 1e-7)[0]}
+            # every truncated form is held to the precision form's 2e-3 T: at |B| = 65^2 the
+            # dropped weight mass alone moves the output by up to 2 eps |B| T / Q (eps = 1.28e-7)
+            oe.sample(v8[name], outb, at8, 2e-3 * T, n=20_000, worst_vs=out8)
+        variants["rect8192_r32_s15"] = v8
+        del big, outb, out8
         # differentiation workload: 16 x 1024^2, r=10, sigma_r=25, N=43
         log("timing 16x1024^2 fwd+bwd")
         pairs = [wl.denoise_pair(i) for i in range(16)]
-        xs = [torch.from_numpy(p[0]).to(dev) for p in pairs]
-        ts = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+        x16 = torch.from_numpy(np.stack([p[0] for p in pairs])).to(dev)
+        t16 = torch.from_numpy(np.stack([p[1] for p in pairs])).to(dev)
 
         def fb16():
-            for x, t in zip(xs, ts):
-                o, s = bilateral_train(x, 10, 25.0, T, 43)
-                gg = (2.0 / x.numel()) * (o - t)
-                bilateral_backward(x, gg, 10, 25.0, T, 43, out=o, saved=s)
+            # the 16 images as one stack: one training-forward launch and one adjoint
+            # launch; loss = mean((u - target)^2) over the batch
+            o, s = bilateral_train(x16, 10, 25.0, T, 43)
+            gg = (2.0 / x16.numel()) * (o - t16)
+            bilateral_backward(x16, gg, 10, 25.0, T, 43, out=o, saved=s)
 
-        ms16, _, _ = time_calls(fb16, 3, 1, stream)
-        variants["denoise16x1024_fwd_bwd"] = {"Mpixel/s": round(16 * 1024 * 1024 / ms16 / 1e3, 2),
-                                              "ms": round(ms16, 3)}
-        del xs, ts, pairs
-        # batched workload: 256 images, one persistent launch replayed from a HIP graph
+        def fb16_each():
+            for b in range(16):
+                o, s = bilateral_train(x16[b], 10, 25.0, T, 43)
+                gg = (2.0 / x16.numel()) * (o - t16[b])
+                bilateral_backward(x16[b], gg, 10, 25.0, T, 43, out=o, saved=s)
+
+        ms16, _, _ = time_calls(fb16, 5, 1, stream)
+        ms16e, _, _ = time_calls(fb16_each, 3, 1, stream)
+        o16, _ = bilateral_train(x16, 10, 25.0, T, 43)
+        x0 = pairs[0][0]
+        v = variants["denoise16x1024_fwd_bwd"] = {"Mpixel/s": round(16 * 1024 * 1024 / ms16 / 1e3, 2),
+                                                  "ms": round(ms16, 3), "one_image_at_a_time_ms": round(ms16e, 3),
+                                                  "error_note": "image 0's training-forward output"}
+        oe.sample(v, o16[0], lambda idx: _oracle().bilateral_at(x0, idx, 10, 25.0, 43), 1e-4 * T, n=50_000)
+        del x16, t16, pairs, o16
+        # batched workload: 256 images, one persistent launch replayed from a HIP graph,
+        # with the default launch shapes and with those the autotuner picks for the batch
         log("generating 256-image batch")
         specs = wl.batch_specs(256, seed=4)
-        imgs = [torch.from_numpy(wl.gradient_image(h, w, s)).to(dev) for (h, w, r, sg, s) in specs]
+        imgs_np = [wl.gradient_image(h, w, s) for (h, w, r, sg, s) in specs]
+        imgs = [torch.from_numpy(x).to(dev) for x in imgs_np]
         outs = [torch.empty_like(x) for x in imgs]
         radii, sigs = [s[2] for s in specs], [s[3] for s in specs]
         tot_px = sum(h * w for (h, w, *_r) in specs)
         side = torch.cuda.Stream()
-        log("timing batched graph")
+        log("timing batched graph (default launch shapes)")
+        tune_cache_clear()
         with torch.cuda.stream(side):
-            ms_bt, _, _ = time_calls(lambda: bilateral_batched(imgs, radii, sigs, T, outs=outs, graph_key=4),
+            ms_b0, _, _ = time_calls(lambda: bilateral_batched(imgs, radii, sigs, T, outs=outs, graph_key=40),
                                      5, 1, side)
-        variants["batched256_graph"] = {"Mpixel/s": round(tot_px / ms_bt / 1e3, 2), "ms": round(ms_bt, 3),
-                                        "pixels": tot_px}
+            log("autotuning the batched launch")
+            t0 = time.perf_counter()
+            blk, _ = autotune_batched(imgs, radii, sigs, T, outs=outs)
+            tune_s = time.perf_counter() - t0
+            log("timing batched graph (tuned launch shapes)")
+            ms_bt, _, _ = time_calls(lambda: bilateral_batched(imgs, radii, sigs, T, outs=outs, graph_key=41),
+                                     5, 1, side)
+        side.synchronize()
+        _, rows_t, chunk_t = batched_shape([tuple(x.shape) for x in imgs], radii, sigs, T)
+        v = variants["batched256_graph"] = {
+            "Mpixel/s": round(tot_px / ms_bt / 1e3, 2), "ms": round(ms_bt, 3), "pixels": tot_px,
+            "default_shape_ms": round(ms_b0, 3), "tuned_block": blk, "tune_s": round(tune_s, 1),
+            "tuned_rows_used": sorted(set(rows_t)), "tuned_chunks_used": sorted(set(chunk_t)), "error": [],
+            "error_note": "images 0, 100 and 255"}
+        for b in (0, 100, 255):
+            _, _, r_, sg_, _ = specs[b]
+            n_b = order_for(sg_, T)
+            oe.sample(v, outs[b], lambda idx, f=imgs_np[b], r_=r_, sg_=sg_, n_b=n_b:
+                      _oracle().bilateral_at(f, idx, r_, sg_, n_b), 1e-4 * T, n=20_000)
+        tune_cache_clear()
         del imgs, outs
         rec["variants"] = variants
 
     if not args.no_cpu:
         log("timing CPU oracle sample")
         rec["cpu_baseline"], rec["parity"] = cpu_baseline(img_np, radius, sigma, N, T, gpu_out=out_head)
+        rec["cpu_baseline"]["host"] = host_info()
+        log("evaluating the variants' errors against the oracle")
+        oe.evaluate()
+    rec["child_processes_at_end"] = child_processes()
     print(json.dumps(rec), flush=True)
 
 
