@@ -193,7 +193,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--kernel-only", nargs="?", const="headline", default=None,
                     choices=["headline", "spatial", "poly", "poly_trunc", "nlm2", "fp64", "fwd_bwd", "bf16",
-                             "batched", "alg1"],
+                             "batched", "alg1", "denoise16"],
                     help="profiling mode: run the headline forward (or the spatial-kernel, polynomial-"
                          "kernel, patch, FP64, training forward + adjoint, 16-bit or Algorithm 1 form at the same "
                          "size, "
@@ -255,6 +255,15 @@ def main():
             def fwd():
                 o, sv = bilateral_train(img, radius, sigma, T, N)
                 bilateral_backward(img, g, radius, sigma, T, N, out=o, saved=sv)
+        elif args.kernel_only == "denoise16":
+            # the 16 x 1024^2 differentiation workload as one stacked launch pair
+            pairs = [wl.denoise_pair(i) for i in range(16)]
+            x16 = torch.from_numpy(np.stack([p[0] for p in pairs])).to(dev)
+            t16 = torch.from_numpy(np.stack([p[1] for p in pairs])).to(dev)
+
+            def fwd():
+                o, sv = bilateral_train(x16, 10, 25.0, T, 43)
+                bilateral_backward(x16, (2.0 / x16.numel()) * (o - t16), 10, 25.0, T, 43, out=o, saved=sv)
         elif args.kernel_only == "alg1":
             # Algorithm 1: the q_2 Gaussian-like spatial filter alone, over the same window
             fwd = lambda: spatial_filter(img, radius, sig_s, 2, out=out)  # noqa: E731

@@ -120,12 +120,16 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // the one with the lower estimated cost, counting the padded orders each pass
 // runs and about 2.5 + kc / 10 orders' worth of per-pass work (window
 // initialisation, recurrence starts, workspace traffic).
-int pick_chunk(int K, int full, int small)
+int pick_chunk(int K, int full, int small, int mid)
 {
     if (small == 0) small = full / 2;
-    if (small < 1 || small == full) return full;
-    auto cost = [K](int kc) { return ((K + kc - 1) / kc) * (kc + 2.5 + 0.1 * kc); };
-    return cost(small) < cost(full) ? small : full;
+    // padded orders plus a per-pass cost (window initialisation, three recurrence
+    // starts per row, workspace traffic) of about 5 + kc / 10 orders
+    auto cost = [K](int kc) { return ((K + kc - 1) / kc) * (kc + 5.0 + 0.1 * kc); };
+    int best = full;
+    if (small >= 1 && small != full && cost(small) < cost(best)) best = small;
+    if (mid > 0 && cost(mid) < cost(best)) best = mid;
+    return best;
 }
 
 std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, double eps)
@@ -367,14 +371,17 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     } else if (kind == kTrain) {
         kc = bsk::chunk_train_f32(block);
     } else if (kind == kBackward) {
-        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_backward_f32(block));
-        if (!bsk::valid_chunk_backward_f32(block, kc))
+        const int mid = bsk::mid_chunk_backward_f32(block);
+        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_backward_f32(block), 0, mid);
+        if (!bsk::valid_chunk_backward_f32(block, kc) && !(mid && kc == mid))
             return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     } else if (r->prec == BSK_FP64) {
         kc = bsk::chunk_forward_f64(block);
     } else {
-        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_forward_f32(block));
-        if (!bsk::valid_chunk_forward_f32(block, kc))
+        // the 12-order pass exists for the plain FP32 stack
+        const int mid = (r->prec == BSK_FP32 && !r->kahan) ? bsk::mid_chunk_forward_f32(block) : 0;
+        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_forward_f32(block), 0, mid);
+        if (!bsk::valid_chunk_forward_f32(block, kc) && !(mid && kc == mid))
             return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     }
     r->kc = kc;

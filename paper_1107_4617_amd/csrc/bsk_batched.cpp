@@ -154,9 +154,15 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     if (max_rh > bsk::max_radius_batched(block))
         return fail(BSK_EUNSUPPORTED, "clamped radius %d too large for a %d-lane strip", max_rh, block);
     const int kfull = bsk::chunk_batched_f32(block);
-    if (o.order_chunk != 0 && o.order_chunk != kfull && o.order_chunk != kfull / 2)
+    const int kmid = bsk::mid_chunk_batched_f32(block);
+    auto pass_size = [&](int kc) { return kc == kfull || kc == kfull / 2 || (kmid > 0 && kc == kmid); };
+    if (o.order_chunk != 0 && !pass_size(o.order_chunk)) {
+        if (kmid > 0)
+            return fail(BSK_EINVAL, "order_chunk %d is not a pass size (%d, %d or %d) of the %d-lane batched kernel",
+                        o.order_chunk, kfull, kmid, kfull / 2, block);
         return fail(BSK_EINVAL, "order_chunk %d is not a pass size (%d or %d) of the %d-lane batched kernel",
                     o.order_chunk, kfull, kfull / 2, block);
+    }
     bp->rows.assign(B, 0);
     bp->chunk.assign(B, 0);
     bp->rbucket.assign(B, 0);
@@ -167,7 +173,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         // rows per unit and orders per pass: the options, else the tuner's sweep,
         // else the measured table, else the defaults (the full pass or its half,
         // whichever pads fewer orders for the cost)
-        int rows = kBatchRows, kc = pick_chunk(it.im.K, kfull);
+        int rows = kBatchRows, kc = pick_chunk(it.im.K, kfull, 0, kmid);
         int ts = 0, tk = 0;
         if (ovr) {
             auto f = ovr->shape.find({it.rb, it.kb});
@@ -178,7 +184,7 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         }
         if (!ts && table) batch_tuned_shape(it.rb, it.kb, prec, block, &ts, &tk);
         if (ts > 0) rows = ts;
-        if (tk == kfull || tk == kfull / 2) kc = tk;
+        if (tk > 0 && pass_size(tk)) kc = tk;
         if (o.strip_h > 0) rows = o.strip_h;
         if (o.order_chunk > 0) kc = o.order_chunk;
         it.im.S = std::min(rows, it.im.H);
@@ -657,8 +663,11 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
         if (b - 2 * base.rh < b / 4 && !(b == 1024 && base.rh <= 511)) continue;
         if (b - 2 * base.rh < 1) continue;
         const int full = bsk::chunk_forward_f32(b);
-        const int kcs[2] = {full, full / 2};
+        // the 12-order pass exists for the plain FP32 stack
+        const int mid = (base.prec == BSK_FP32 && !base.kahan) ? bsk::mid_chunk_forward_f32(b) : 0;
+        const int kcs[3] = {full, mid, full / 2};
         for (int kc : kcs) {
+            if (kc <= 0) continue;
             // the FP64 forward has a single pass size
             if (base.prec == BSK_FP64 && kc != full) continue;
             for (int S : rows) {
@@ -802,7 +811,9 @@ int bsk_autotune_batched(const bsk_image_desc *descs, int B, float T, const bsk_
             const int S = rows_c[si];
             // units taller than the bucket's tallest image are all the same shape
             if (si > 0 && rows_c[si - 1] >= hmax[key]) break;
-            for (int kc : {kfull, kfull / 2}) {
+            const int kmid = bblock ? bsk::mid_chunk_batched_f32(bblock) : 0;
+            for (int kc : {kfull, kmid, kfull / 2}) {
+                if (kc <= 0) continue;
                 BatchShapeOverride v = ovr;
                 v.shape[key] = {S, kc};
                 double ms = 0.0;

@@ -18,6 +18,9 @@ constexpr int wg_batched(int block) { return block == 256 ? 3 : 2; }
 int wg_per_cu_batched(int block) { return wg_batched(block); }
 
 int chunk_batched_f32(int block) { return kc_batched(block); }
+// the 12-order pass of the 256-lane kernel (0: none), as for the single-image forward
+constexpr int kmid_batched(int block) { return block == 256 ? 12 : 0; }
+int mid_chunk_batched_f32(int block) { return kmid_batched(block); }
 int max_radius_batched(int block) { return (block - 2) / 2; }
 
 __global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
@@ -71,10 +74,14 @@ __global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const
         gm.sp_u0 = 1.0f;   // the box spatial kernel
         for (int j = 0; j < kMaxSpatialFreq; ++j) gm.sp_u[j] = 0.0f;
         gm.sp_row = gm.sp_col = nullptr;
-        // the image's pass size: the full pass or its half (same LDS shape)
+        // the image's pass size: the full pass, its half or (256 lanes) 12 orders (same LDS shape)
+        constexpr int KM = kmid_batched(BLOCK);
         if (im.kc == KC)
             strip_body<float, BLOCK, KC, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
                                                                                         nullptr, nullptr);
+        else if (KM > 0 && im.kc == KM)
+            strip_body<float, BLOCK, (KM > 0 ? KM : KC), kl_batched(BLOCK), PolForward<float>, 0, false>(
+                io, gm, bx, by, lds, nullptr, nullptr);
         else
             strip_body<float, BLOCK, KC / 2, kl_batched(BLOCK), PolForward<float>, 0, false>(io, gm, bx, by, lds,
                                                                                             nullptr, nullptr);

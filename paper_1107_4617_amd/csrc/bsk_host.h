@@ -59,9 +59,10 @@ enum Kind { kForward = 0, kTrain = 1, kBackward = 2, kPatch2 = 3 };
 // resident workgroups the segment height is chosen for).
 int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options *opt, Resolved *r,
             int kind = kForward, int nimg = 1);
-// Orders per pass from a kernel family's full pass and a smaller one (0: half
-// the full one): the one with the lower estimated cost for K orders.
-int pick_chunk(int K, int full, int small = 0);
+// Orders per pass from a kernel family's full pass, a smaller one (0: half
+// the full one) and optionally a third size between them (0: none): the one
+// with the lower estimated cost for K orders.
+int pick_chunk(int K, int full, int small = 0, int mid = 0);
 // Plan of the polynomial range kernel, cached per (N, sigma_r, T, eps).
 std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, double eps);
 // Fills the launch arguments; the weights are padded with zeros to a multiple

@@ -201,6 +201,10 @@ bool spatial_block_ok(int block, int nsc);
 // forward and the adjoint offer a full and a half pass size per block.
 bool valid_chunk_forward_f32(int block, int kc);
 bool valid_chunk_backward_f32(int block, int kc);
+// The 12-order pass of the 256-lane plain FP32 forward and adjoint (0 for
+// other lane counts).
+int mid_chunk_forward_f32(int block);
+int mid_chunk_backward_f32(int block);
 int chunk_forward_f32(int block);
 int chunk_forward_f64(int block);
 int chunk_train_f32(int block);
@@ -235,6 +239,7 @@ struct BatchArgs {
 
 hipError_t launch_batched_f32(const BatchArgs &a, int block, int grid, hipStream_t s);
 int chunk_batched_f32(int block);
+int mid_chunk_batched_f32(int block);   // 12 for 256 lanes, else 0
 // Largest clamped radius the batched kernel of a given block size accepts.
 int max_radius_batched(int block);
 int wg_per_cu_batched(int block);

@@ -217,6 +217,12 @@ bool valid_chunk_backward_f32(int block, int kc)
 {
     return kc == kr_bwd(block) || kc == kr_bwd(block) / 2;
 }
+// A third pass size between the full and the half one, for 256-lane strips:
+// 12 orders still fit three workgroups per CU (117 VGPRs for the plain FP32
+// forward, 166 for the adjoint), and orders counts such as 22 then take two
+// passes instead of three (or two padded ones of 16).
+int mid_chunk_forward_f32(int block) { return block == 256 ? 12 : 0; }
+int mid_chunk_backward_f32(int block) { return block == 256 ? 12 : 0; }
 int chunk_forward_f32(int block) { return kr_f32(block); }
 int chunk_forward_f64(int block) { return kr_f64(block); }
 int chunk_train_f32(int block) { return kr_train(block); }
@@ -249,9 +255,23 @@ static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *oc
     return launch<float, BLOCK, KR / 2, KL, PolForward<float>, QUANT, KAHAN, MINB>(a, s, occ);
 }
 
+// The 12-order pass of the plain FP32 256-lane forward (one-pass launches with
+// the start mode as a constant, like the other pass sizes).
+static hipError_t fwd32_mid(const StripArgs &a, hipStream_t s, int *occ)
+{
+    constexpr int KR = 12, KL = 4;
+    if (a.K <= KR && (a.start_mode == 0 || a.start_mode == 1))
+        return a.start_mode == 0 ? launch<float, 256, KR, KL, PolForward<float, 0>, 0, false, 3>(a, s, occ)
+                                 : launch<float, 256, KR, KL, PolForward<float, 1>, 0, false, 3>(a, s, occ);
+    return launch<float, 256, KR, KL, PolForward<float>, 0, false, 3>(a, s, occ);
+}
+
 template <int QUANT, bool KAHAN>
 static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
+    if constexpr (QUANT == 0 && !KAHAN) {
+        if (block == 256 && kc == mid_chunk_forward_f32(256)) return fwd32_mid(a, s, occ);
+    }
     switch (block) {
     case 256: return fwd32_block<256, QUANT, KAHAN>(a, kc, s, occ);
     case 512: return fwd32_block<512, QUANT, KAHAN>(a, kc, s, occ);
@@ -262,7 +282,8 @@ static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s, in
 
 hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s, int *occ)
 {
-    if (!valid_chunk_forward_f32(block, kc)) return hipErrorInvalidValue;
+    const bool mid = prec == 0 && !kahan && kc == mid_chunk_forward_f32(block);
+    if (!valid_chunk_forward_f32(block, kc) && !mid) return hipErrorInvalidValue;
     if (prec == 1) return kahan ? fwd32<1, true>(a, block, kc, s, occ) : fwd32<1, false>(a, block, kc, s, occ);
     if (prec == 2) return kahan ? fwd32<2, true>(a, block, kc, s, occ) : fwd32<2, false>(a, block, kc, s, occ);
     if (prec == 4) return kahan ? fwd32<4, true>(a, block, kc, s, occ) : fwd32<4, false>(a, block, kc, s, occ);
@@ -349,6 +370,9 @@ static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
     constexpr int KR = kr_bwd(BLOCK), KL = kl_bwd(BLOCK);
     if (kc == KR) return bwd<BLOCK, KR, KL, 0>(a, s, occ);
+    if constexpr (BLOCK == 256) {
+        if (kc == mid_chunk_backward_f32(256)) return bwd<256, 12, 4, 3>(a, s, occ);
+    }
     // the half pass of 256 lanes fits three workgroups per compute unit
     return bwd<BLOCK, KR / 2, (KL < KR / 2 ? KL : KR / 2), BLOCK == 256 ? 3 : 0>(a, s, occ);
 }
@@ -434,7 +458,7 @@ hipError_t launch_phase_table(const SpatialPlan &sp, int n, float *tab, hipStrea
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ)
 {
-    if (!valid_chunk_backward_f32(block, kc)) return hipErrorInvalidValue;
+    if (!valid_chunk_backward_f32(block, kc) && kc != mid_chunk_backward_f32(block)) return hipErrorInvalidValue;
     hipError_t e;
     switch (block) {
     case 256: e = bwd_block<256>(a, kc, s, occ); break;

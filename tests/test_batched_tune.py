@@ -19,10 +19,16 @@ def _n0(sigma, T=255.0):
     return math.ceil((2 * T / (math.pi * sigma)) ** 2)
 
 
-def _default_chunk(K, full=16):
-    # the pass size with the lower estimated cost, as the library picks it
-    cost = lambda kc: ((K + kc - 1) // kc) * (kc + 2.5 + 0.1 * kc)  # noqa: E731
-    return full // 2 if cost(full // 2) < cost(full) else full
+def _default_chunk(K, full=16, mid=12):
+    # the pass size with the lower estimated cost, as the library picks it (ties keep the
+    # full pass, then the half pass)
+    cost = lambda kc: ((K + kc - 1) // kc) * (kc + 5.0 + 0.1 * kc)  # noqa: E731
+    best = full
+    if cost(full // 2) < cost(best):
+        best = full // 2
+    if mid and cost(mid) < cost(best):
+        best = mid
+    return best
 
 
 def _rb(r):
@@ -57,8 +63,11 @@ def test_options_fix_the_shape(clean_cache):
     assert block == 256 and rows == [min(40, h) for h, _ in SHAPES] and chunk == [8] * 4
     block, rows, chunk = batched_shape(SHAPES, RADII, SIGMAS, block=512)
     assert block == 512 and set(chunk) <= {8, 4}
+    assert batched_shape(SHAPES, RADII, SIGMAS, order_chunk=12)[2] == [12] * 4
     with pytest.raises(_lib.BskError):
         batched_shape(SHAPES, RADII, SIGMAS, order_chunk=5)   # not a pass size of the kernel
+    with pytest.raises(_lib.BskError):
+        batched_shape(SHAPES, RADII, SIGMAS, block=512, order_chunk=12)   # 12 exists for 256 lanes only
     with pytest.raises(_lib.BskError):
         batched_shape(SHAPES, [300] + RADII[1:], SIGMAS, block=256)   # radius beyond a 256-lane strip
 

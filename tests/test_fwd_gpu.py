@@ -91,6 +91,8 @@ def test_fp64_matches_oracle(shape, r, N, sigma, block):
     ((70, 300), 8, 31, 30.0, 0, 0),         # odd N filling one 16-order pass
     ((70, 300), 8, 29, 30.0, 256, 0),       # odd N, 15 orders in a 16-order pass
     ((80, 600), 70, 30, 30.0, 512, 20),     # 512-lane strips
+    ((90, 300), 6, 20, 36.0, 256, 0),       # 11 orders, one 12-order pass (N_0 = 20 at sigma_r = 36)
+    ((90, 300), 6, 43, 25.0, 256, 0),       # 22 orders, two 12-order passes
     ((40, 1100), 200, 30, 30.0, 1024, 0),   # 1024-lane strips
     ((12, 1100), 500, 30, 30.0, 0, 0),      # the largest clamped radius (BSK_MAX_RADIUS)
 ])
@@ -99,6 +101,16 @@ def test_shapes_and_edge_cases(shape, r, N, sigma, block, strip_h):
     f = wl.random_image(*shape, seed=sum(shape) + r)
     ref = oracle.bilateral(f, r, sigma, N)
     out = _gpu_filter(f, r, sigma, N=N, block=block, strip_h=strip_h)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
+@pytest.mark.parametrize("kc", [8, 12, 16])
+def test_every_pass_size(kc):
+    """30 folded orders (N = 59) in passes of 8, 12 or 16 orders (4, 3 or 2 passes, the last
+    one padded) against the oracle."""
+    f = wl.rect_image(100, 300, seed=59, n_rect=10)
+    ref = oracle.bilateral(f, 7, 22.0, 59)
+    out = _gpu_filter(f, 7, 22.0, N=59, block=256, order_chunk=kc)
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
