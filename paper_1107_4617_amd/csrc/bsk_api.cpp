@@ -195,7 +195,7 @@ static int kernel_occupancy(const Resolved &r, int kind)
     } else if (r.sp.Ns > 0) {
         (void)bsk::launch_spatial_f32(a, r.block, r.sp, r.kc, nullptr, &occ);
     } else if (kind == kTrain) {
-        (void)bsk::launch_train_f32(a, r.block, nullptr, &occ);
+        (void)bsk::launch_train_f32(a, r.block, r.kc, nullptr, &occ);
     } else if (kind == kBackward) {
         (void)bsk::launch_backward_f32(a, r.block, r.kc, nullptr, 0.0, 0, nullptr, &occ);
     } else if (r.prec == BSK_FP64) {
@@ -763,7 +763,7 @@ int train_impl(const float *img, int B, int H, int W, const Resolved &r, float *
         a.ws = ws;
         a.bs_ws = bsk::acc_count_train() * plane;
     }
-    hipError_t e = bsk::launch_train_f32(a, r.block, (hipStream_t)stream);
+    hipError_t e = bsk::launch_train_f32(a, r.block, r.kc, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "train launch");
     return BSK_OK;
 }

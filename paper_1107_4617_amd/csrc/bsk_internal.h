@@ -178,7 +178,7 @@ int chunk_poly_f64(int block);
 hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s,
                               int *occ = nullptr);
 hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
-hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
+hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);
 // FP32 forward of the two-pixel-patch filter (orders per pass kc, one of the

@@ -343,8 +343,10 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int 
     }
 }
 
-hipError_t launch_train_f32(const StripArgs &a, int block, hipStream_t s, int *occ)
+hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
+    // (a 12-order pass measured 6% slower than three of 8 on 22 orders at 1024^2)
+    if (kc != kr_train(block)) return hipErrorInvalidValue;
     switch (block) {
     case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3>(a, s, occ);
     case 512: return launch<float, 512, kr_train(512), kl_train(512), PolTrain, 0, false>(a, s, occ);
