@@ -371,8 +371,17 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
     } else if (kind == kTrain) {
         kc = bsk::chunk_train_f32(block);
     } else if (kind == kBackward) {
-        const int mid = bsk::mid_chunk_backward_f32(block);
-        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_backward_f32(block), 0, mid);
+        const int full = bsk::chunk_backward_f32(block), mid = bsk::mid_chunk_backward_f32(block);
+        if (kc == 0) {
+            // Measured per padded order (256 lanes, 4096^2 and 16 x 1024^2): the full
+            // pass at two workgroups per CU costs 1, the 12-order pass 1.38 and the
+            // half pass 1.55 (both at three per CU), so the full pass wins unless the
+            // half pass saves a whole pass of it.
+            auto cost = [&](int c, double w) { return (double)((r->plan.K + c - 1) / c) * c * w; };
+            kc = full;
+            if (mid && cost(mid, 1.38) < cost(kc, 1.0)) kc = mid;
+            if (cost(full / 2, 1.55) < cost(kc, kc == full ? 1.0 : 1.38)) kc = full / 2;
+        }
         if (!bsk::valid_chunk_backward_f32(block, kc) && !(mid && kc == mid))
             return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     } else if (r->prec == BSK_FP64) {
