@@ -27,6 +27,7 @@ struct BatchPlan {
     int block = 256;
     std::vector<int> rows, chunk;   // per descriptor, in descriptor order: rows per unit, orders per pass
     std::vector<int> rbucket, kbucket;
+    int qstart[bsk::kBatchQueues + 1] = {};   // per-XCD queues of units (BatchArgs::qstart)
 };
 
 constexpr int kBatchRows = 96;   // default output rows per work unit (64: 1% slower on the 256-image batch)
@@ -209,10 +210,41 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
     bp->vtab.clear();
     bp->vtabf.clear();
     bp->ws_elems = 0;
+    // One queue per XCD: images go, most expensive unit first, to the queue with
+    // the least work so far (so every queue also ends with its cheapest units),
+    // and each queue's images are numbered contiguously.
+    {
+        double load[bsk::kBatchQueues] = {};
+        std::vector<int> queue(items.size());
+        for (size_t i = 0; i < items.size(); ++i) {
+            int best = 0;
+            for (int q = 1; q < bsk::kBatchQueues; ++q)
+                if (load[q] < load[best]) best = q;
+            queue[i] = best;
+            load[best] += items[i].cost;
+        }
+        std::vector<Item> byq;
+        byq.reserve(items.size());
+        for (int q = 0; q < bsk::kBatchQueues; ++q)
+            for (size_t i = 0; i < items.size(); ++i)
+                if (queue[i] == q) byq.push_back(std::move(items[i]));
+        // queue boundaries in image indices, turned into unit indices below
+        int qi = 0;
+        bp->qstart[0] = 0;
+        for (int q = 0; q < bsk::kBatchQueues; ++q) {
+            for (size_t i = 0; i < queue.size(); ++i) qi += queue[i] == q;
+            bp->qstart[q + 1] = qi;   // image index where queue q + 1 begins
+        }
+        items = std::move(byq);
+    }
     long long units = 0;
+    std::vector<int> img_unit0;
+    img_unit0.reserve(items.size() + 1);
     for (auto &it : items) {
         it.im.unit0 = (int)units;
-        units += (long long)it.im.strips * ((it.im.H + it.im.S - 1) / it.im.S);
+        img_unit0.push_back((int)units);
+        const long long nu = (long long)it.im.strips * ((it.im.H + it.im.S - 1) / it.im.S);
+        units += nu;
         if (units > (1LL << 30)) return fail(BSK_EINVAL, "too many work units");
         it.im.v_off = (int)bp->vtab.size();
         // pad to whole passes with zero weights
@@ -229,6 +261,8 @@ int build_batch(const bsk_image_desc *d, int B, float T, const bsk_options *opt,
         }
         bp->imgs.push_back(it.im);
     }
+    img_unit0.push_back((int)units);
+    for (int q = 0; q <= bsk::kBatchQueues; ++q) bp->qstart[q] = img_unit0[bp->qstart[q]];
     bp->total_units = (int)units;
     bp->block = block;
     return BSK_OK;
@@ -275,6 +309,7 @@ void set_args(DeviceBatch *db, const BatchPlan &bp, size_t off_v, size_t off_f, 
     db->args.ws = db->ws;
     db->args.nimg = (int)bp.imgs.size();
     db->args.total_units = bp.total_units;
+    for (int q = 0; q <= bsk::kBatchQueues; ++q) db->args.qstart[q] = bp.qstart[q];
 }
 
 // Pinned staging for the per-call table upload: one per stream; reused only

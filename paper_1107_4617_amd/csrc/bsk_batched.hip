@@ -1,10 +1,11 @@
 // Persistent batched kernel: many images of different sizes, radii and
 // sigma_r in one launch.  Each workgroup repeatedly claims a work unit
-// (image, strip, row segment) from a device counter and runs the same fused
+// (image, strip, row segment) from device counters and runs the same fused
 // strip body as the single-image forward kernel on it; the loop ends for
-// every workgroup once the counter passes the last unit, so the grid always
-// drains.  Units are numbered image by image in the order of the host table,
-// which lists the most expensive images first.
+// every workgroup once every queue's counter has passed its last unit, so the
+// grid always drains.  Units are numbered image by image in the order of the
+// host table, which lists the most expensive images first, and cut into one
+// contiguous queue per XCD of about equal cost.
 #include "bsk_device.h"
 
 namespace bsk {
@@ -23,19 +24,36 @@ constexpr int kmid_batched(int block) { return block == 256 ? 12 : 0; }
 int mid_chunk_batched_f32(int block) { return kmid_batched(block); }
 int max_radius_batched(int block) { return (block - 2) / 2; }
 
-__global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
+__global__ void reset_counter_kernel(unsigned *counter)
+{
+    if (threadIdx.x < kBatchQueues) counter[threadIdx.x] = 0u;
+}
 
 template <int BLOCK, int KC>
 __global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const BatchArgs a)
 {
     __shared__ __align__(16) float lds[strip_lds_elems<PolForward<float>::NCH, kl_batched(BLOCK), BLOCK>()];
     __shared__ int unit_sh;
+    // the XCD this workgroup runs on: workgroups are dispatched to the XCDs
+    // round-robin by linear index
+    const int home = blockIdx.x % kBatchQueues;
     for (;;) {
-        if (threadIdx.x == 0) unit_sh = (int)atomicAdd(a.counter, 1u);
+        if (threadIdx.x == 0) {
+            // the home queue first, then the others in turn; -1 once all are empty
+            int u = -1;
+            for (int k = 0; k < kBatchQueues && u < 0; ++k) {
+                const int q = (home + k) % kBatchQueues;
+                const int len = a.qstart[q + 1] - a.qstart[q];
+                if (len <= 0) continue;
+                const int v = (int)atomicAdd(a.counter + q, 1u);
+                if (v < len) u = a.qstart[q] + v;
+            }
+            unit_sh = u;
+        }
         __syncthreads();
         const int unit = unit_sh;
         __syncthreads();
-        if (unit >= a.total_units) break;
+        if (unit < 0) break;
         // image owning this unit: last entry with unit0 <= unit
         int lo = 0, hi = a.nimg - 1;
         while (lo < hi) {
@@ -91,7 +109,7 @@ __global__ void __launch_bounds__(BLOCK, wg_batched(BLOCK)) batched_kernel(const
 
 hipError_t launch_batched_f32(const BatchArgs &a, int block, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.counter);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, a.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (block) {

@@ -227,6 +227,7 @@ struct BatchImage {
     double omega_base, delta;
 };
 
+constexpr int kBatchQueues = 8;   // one work queue per XCD
 struct BatchArgs {
     const BatchImage *imgs;  // device table, ordered by unit0
     const double *vtab;      // device folded weights (each image padded to a pass)
@@ -234,7 +235,13 @@ struct BatchArgs {
     float *ws;               // partial accumulators for images with K > chunk
     int nimg;
     int total_units;
-    unsigned *counter;       // device work counter, zeroed by a kernel before each launch
+    // Units [qstart[q], qstart[q + 1]) form queue q, served first by the
+    // workgroups of XCD q (contiguous runs of units share image rows and columns
+    // in that XCD's L2); a workgroup whose queue is empty takes units from the
+    // others.  counter holds one claim counter per queue, zeroed by a kernel
+    // before each launch.
+    int qstart[kBatchQueues + 1];
+    unsigned *counter;
 };
 
 hipError_t launch_batched_f32(const BatchArgs &a, int block, int grid, hipStream_t s);

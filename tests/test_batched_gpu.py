@@ -66,8 +66,11 @@ def test_full_batch_256_images():
     specs = wl.batch_specs(256, seed=4)
     imgs = [torch.from_numpy(wl.gradient_image(H, W, s)).cuda() for (H, W, r, sg, s) in specs]
     radii, sig = [s[2] for s in specs], [s[3] for s in specs]
-    outs = bilateral_batched(imgs, radii, sig, T)
+    # every output pixel is written exactly by some work unit of some queue
+    outs = [torch.full_like(x, float("nan")) for x in imgs]
+    bilateral_batched(imgs, radii, sig, T, outs=outs)
     torch.cuda.synchronize()
+    assert all(bool(torch.isfinite(o).all()) for o in outs)
     rng = np.random.default_rng(4)
     for b in rng.choice(256, 6, replace=False):
         H, W, r, sg, _ = specs[b]
