@@ -199,7 +199,7 @@ static int kernel_occupancy(const Resolved &r, int kind)
     } else if (kind == kBackward) {
         (void)bsk::launch_backward_f32(a, r.block, r.kc, nullptr, 0.0, 0, nullptr, &occ);
     } else if (r.prec == BSK_FP64) {
-        (void)bsk::launch_forward_f64(a, r.block, nullptr, &occ);
+        (void)bsk::launch_forward_f64(a, r.block, r.kc, nullptr, &occ);
     } else {
         (void)bsk::launch_forward_f32(a, r.block, r.kc, r.prec, r.kahan, nullptr, &occ);
     }
@@ -385,7 +385,10 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         if (!bsk::valid_chunk_backward_f32(block, kc) && !(mid && kc == mid))
             return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     } else if (r->prec == BSK_FP64) {
-        kc = bsk::chunk_forward_f64(block);
+        // one pass of up to 16 orders with the start mode as a constant where the
+        // plan allows it, else passes of the general kernel
+        const int one = bsk::onepass_chunk_forward_f64(block);
+        kc = (one && r->plan.K <= one && r->plan.start_mode <= 1) ? one : bsk::chunk_forward_f64(block);
     } else {
         // the 12-order pass exists for the plain FP32 stack
         const int mid = (r->prec == BSK_FP32 && !r->kahan) ? bsk::mid_chunk_forward_f32(block) : 0;
@@ -746,7 +749,7 @@ int forward_impl(const void *img, int H, int W, int radius, float sigma_r, float
         return BSK_OK;
     }
     hipError_t e = r.prec == BSK_FP64
-                       ? bsk::launch_forward_f64(a, r.block, (hipStream_t)stream)
+                       ? bsk::launch_forward_f64(a, r.block, r.kc, (hipStream_t)stream)
                        : bsk::launch_forward_f32(a, r.block, r.kc, r.prec, r.kahan, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return BSK_OK;

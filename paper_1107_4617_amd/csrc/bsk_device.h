@@ -526,6 +526,23 @@ struct PolTrain {
     }
 };
 
+// Policies whose recombination uses each order's weight only as a factor of
+// all its box-sum terms (v_m, or v_m omega_m): the H stage then scales the
+// prefix rows of order m by v_m, and the R stage takes v = 1 and omega_m in
+// place of v_m omega_m.
+template <class P>
+struct FoldsWeight {
+    static constexpr bool value = false;
+};
+template <typename FT, int SM>
+struct FoldsWeight<PolForward<FT, SM>> {
+    static constexpr bool value = true;
+};
+template <>
+struct FoldsWeight<PolTrain> {
+    static constexpr bool value = true;
+};
+
 // Backward (adjoint): with alpha = gbar / Q and ut = u - ref, channels
 // (alpha C, alpha S, alpha ut C, alpha ut S); one accumulator
 //   T1(z) = sum_m v_m { C(z) Box[aC] + S(z) Box[aS]
@@ -590,6 +607,10 @@ struct PolBackward {
         if (a.out) ((float *)a.out)[o] = (float)(acc[0] - alpha * (AT)a.aux3[o]);
         *red += (double)alpha * (double)a.aux4[o];
     }
+};
+template <>
+struct FoldsWeight<PolBackward> {
+    static constexpr bool value = true;
 };
 
 // ---------------------------------------------------------------- the body --
@@ -719,10 +740,38 @@ constexpr int strip_lds_elems()
 // Exclusive prefix sums over aligned groups of CH consecutive lanes (CH a power
 // of two, at most 64); wch is the lane's index in its group.  Groups of 16 are
 // DPP rows: four shifted adds within the row and one final shift, no LDS.
+// A DPP lane move of a 64-bit value: both 32-bit halves with the same control;
+// lanes that the control leaves without a source (or rows outside row_mask)
+// read zero.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 template <int CH, typename AT>
 __device__ __forceinline__ AT group_exclusive_scan(AT x, int wch)
 {
-    if constexpr (CH == 16 && sizeof(AT) == 4) {
+    if constexpr ((CH == 16 || CH == 32) && sizeof(AT) == 8) {
+        // FP64: the same row scans on the two halves; groups of 32 add the last
+        // lane of the lower row to the upper one (row_bcast:15, rows 1 and 3)
+        // and shift across the row boundary (wave_shr:1, zero at a group's first lane)
+        double y = x;
+        y += dpp64<0x111, 0xf>(y);
+        y += dpp64<0x112, 0xf>(y);
+        y += dpp64<0x114, 0xf>(y);
+        y += dpp64<0x118, 0xf>(y);
+        if constexpr (CH == 16) {
+            return dpp64<0x111, 0xf>(y);
+        } else {
+            y += dpp64<0x142, 0xa>(y);
+            const double e = dpp64<0x138, 0xf>(y);
+            return wch == 0 ? 0.0 : e;
+        }
+    } else if constexpr (CH == 16 && sizeof(AT) == 4) {
         // row_shr:n (dpp_ctrl 0x110 + n) reads lane l - n of the same row; the
         // first n lanes of the row read zero (bound_ctrl)
         float y = x;
@@ -846,6 +895,15 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
 
     double red = 0.0;
 
+    // The order of this lane's walker row within an interval: rows are ordered
+    // (order k, pair, horizontal basis row, member), NCH NB rows per order.
+    // When the rows of one wavefront all belong to one order the index is made
+    // wave-uniform, so that the weights come from scalar loads.
+    constexpr bool FOLDV = FoldsWeight<POL>::value;
+    constexpr int RPW = 64 / CH;   // walker rows per wavefront
+    int kw = min(wrow, ROWS - 1) / (NCH * NB);
+    if constexpr (RPW <= NCH * NB && (NCH * NB) % RPW == 0) kw = __builtin_amdgcn_readfirstlane(kw);
+
     // POL::START >= 0: one pass (K <= KR) whose chain start mode is that constant
     constexpr int CSTART = POL::START;
     const int Kloop = CSTART >= 0 ? 1 : gm.K;
@@ -876,6 +934,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
             om1 = (AT)(gm.p2_omega1_base + (double)n1 * gm.p2_delta1);
             d1 = (AT)gm.p2_delta1;
         }
+
+        // weights of the walker rows of each sub-phase (FOLDV)
+        AT vH[FOLDV ? NSUB : 1];
+#pragma unroll
+        for (int s = 0; s < (FOLDV ? NSUB : 1); ++s) vH[s] = FOLDV ? weight<AT>(gm, m0 + s * KL + kw) : AT(1);
 
         AT V[KR][NCH];
         AT Cmp[KAHAN ? KR : 1][NCH];
@@ -1072,6 +1135,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         chain_restart<POL>(cc, m);
                         AT v;
                         if constexpr (IsPatch2<POL>::value) v = ((ConstPtr<float>)gm.p2_vf)[m0 + m];
+                        else if constexpr (FOLDV) v = AT(1);   // already in B
                         else v = weight<AT>(gm, m0 + m);
                         const AT vom = v * (om0 + (AT)m * dlt);
                         if constexpr (CSTART == 0) {
@@ -1106,9 +1170,18 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     }
                     const AT off = group_exclusive_scan<CH>(run, wch);
                     if (walker) {
-                        VbH[wbase] = off;
+                        if constexpr (FOLDV) {
+                            // the prefixes of order m scaled by its weight v_m
+                            const AT vw = vH[floormod(h - 1, NSUB)];
+                            const AT offv = off * vw;
+                            VbH[wbase] = offv;
 #pragma unroll
-                        for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
+                            for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = fmat(loc[u], vw, offv);
+                        } else {
+                            VbH[wbase] = off;
+#pragma unroll
+                            for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
+                        }
                     }
                 }
 

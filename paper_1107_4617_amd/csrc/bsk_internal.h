@@ -177,7 +177,7 @@ int chunk_poly_f64(int block);
 // kernel it would launch that one compute unit holds.
 hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s,
                               int *occ = nullptr);
-hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int *occ = nullptr);
+hipError_t launch_forward_f64(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);
@@ -207,6 +207,7 @@ int mid_chunk_forward_f32(int block);
 int mid_chunk_backward_f32(int block);
 int chunk_forward_f32(int block);
 int chunk_forward_f64(int block);
+int onepass_chunk_forward_f64(int block);   // 0: none for this lane count
 int chunk_train_f32(int block);
 int chunk_backward_f32(int block);
 int acc_count_forward();   // accumulators per pixel kept across chunks

@@ -333,8 +333,23 @@ hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, int pack, hi
     }
 }
 
-hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int *occ)
+// One-pass FP64 forward of 256 lanes: 16 orders in registers, two per
+// interval (the three row buffers take 55 KiB, so two workgroups share a
+// compute unit), with the chain start mode as a constant.  Up to 16 folded
+// orders (N up to 31) then need no accumulator planes and one chain start
+// per pixel and use.
+constexpr int kr_f64_one(int block) { return block == 256 ? 16 : 0; }
+int onepass_chunk_forward_f64(int block) { return kr_f64_one(block); }
+
+hipError_t launch_forward_f64(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
+    if (block == 256 && kc == kr_f64_one(256)) {
+        constexpr int KR = kr_f64_one(256), KL = kl_f64(256);
+        if (!occ && (a.K > KR || (a.start_mode != 0 && a.start_mode != 1))) return hipErrorInvalidValue;
+        return a.start_mode == 1 ? launch<double, 256, KR, KL, PolForward<double, 1>, 0, false, 2>(a, s, occ)
+                                 : launch<double, 256, KR, KL, PolForward<double, 0>, 0, false, 2>(a, s, occ);
+    }
+    if (kc != kr_f64(block)) return hipErrorInvalidValue;
     switch (block) {
     case 256: return launch<double, 256, kr_f64(256), kl_f64(256), PolForward<double>, 0, false>(a, s, occ);
     case 512: return launch<double, 512, kr_f64(512), kl_f64(512), PolForward<double>, 0, false>(a, s, occ);
@@ -345,7 +360,9 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, hipStream_t s, int 
 
 hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
-    // (a 12-order pass measured 6% slower than three of 8 on 22 orders at 1024^2)
+    // (a 12-order pass measured 6% slower than three of 8 on 22 orders at 1024^2,
+    // and one 16-order pass at two workgroups per CU 3% slower than two of 8 on
+    // 16 orders at 4096^2)
     if (kc != kr_train(block)) return hipErrorInvalidValue;
     switch (block) {
     case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3>(a, s, occ);

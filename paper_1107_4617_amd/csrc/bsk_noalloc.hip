@@ -71,7 +71,7 @@ int bilateral_shiftable_noalloc(const void *img, int H, int W, int radius, float
     a.io.out = out;
     if (need > 0) a.ws = p;
     const hipError_t e = r.prec == BSK_FP64
-                             ? bsk::launch_forward_f64(a, r.block, (hipStream_t)stream)
+                             ? bsk::launch_forward_f64(a, r.block, r.kc, (hipStream_t)stream)
                              : bsk::launch_forward_f32(a, r.block, r.kc, r.prec, r.kahan, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return BSK_OK;

@@ -61,10 +61,11 @@ def test_smooth256_fp64_and_fp32():
 
 
 @pytest.mark.parametrize("shape,r,N,sigma,block", [
-    ((70, 300), 8, 31, 30.0, 0),       # odd N, two passes of 8 orders
-    ((70, 300), 8, 7, 70.0, 0),        # odd N, one pass
+    ((70, 300), 8, 31, 30.0, 0),       # odd N, 16 orders: the one-pass FP64 kernel
+    ((150, 500), 12, 30, 30.0, 0),     # even N, 16 orders, one pass over several strips and segments
+    ((70, 300), 8, 7, 70.0, 0),        # odd N, one pass (4 orders padded to 16)
     ((60, 90), 6, 8, 60.0, 0),         # even N, one pass
-    ((129, 257), 20, 43, 25.0, 256),   # 22 orders, three passes
+    ((129, 257), 20, 43, 25.0, 256),   # 22 orders: three passes of 8 orders
     ((80, 600), 70, 30, 30.0, 512),    # 512-lane strips
 ])
 def test_fp64_matches_oracle(shape, r, N, sigma, block):
