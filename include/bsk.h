@@ -96,7 +96,7 @@ typedef struct {
     int strip_h;          /* output rows per workgroup; 0 = auto */
     int order_chunk;      /* orders per pass, one of the pass sizes of the kernel that runs:
                              FP32 forward 256: 16|12|8 (12: plain FP32 stack only), 512: 8|4,
-                             1024: 4|2 (lanes: full|half); adjoint 256: 16|12|8, 512: 8|4,
+                             1024: 4|2 (lanes: full|half); adjoint 256: 24|16|12|8, 512: 8|4,
                              1024: 2|1; batched 256: 16|12|8, 512: 8|4, 1024: 4|2; spatial kernel 4|2
                              (one frequency) or 2|1; polynomial range kernel (channel pairs)
                              256 and 512: 16|8, 1024: 8|4; ignored by FP64 and the training

@@ -372,17 +372,21 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         kc = bsk::chunk_train_f32(block);
     } else if (kind == kBackward) {
         const int full = bsk::chunk_backward_f32(block), mid = bsk::mid_chunk_backward_f32(block);
+        const int big = bsk::big_chunk_backward_f32(block);
         if (kc == 0) {
             // Measured per padded order (256 lanes, 4096^2 and 16 x 1024^2): the full
             // pass at two workgroups per CU costs 1, the 12-order pass 1.38 and the
             // half pass 1.55 (both at three per CU), so the full pass wins unless the
-            // half pass saves a whole pass of it.
+            // half pass saves a whole pass of it.  The 24-order pass (two per CU)
+            // costs 0.93 (one pass of 24 against two of 16 on 22 orders).
             auto cost = [&](int c, double w) { return (double)((r->plan.K + c - 1) / c) * c * w; };
             kc = full;
-            if (mid && cost(mid, 1.38) < cost(kc, 1.0)) kc = mid;
-            if (cost(full / 2, 1.55) < cost(kc, kc == full ? 1.0 : 1.38)) kc = full / 2;
+            double best = cost(full, 1.0);
+            if (mid && cost(mid, 1.38) < best) kc = mid, best = cost(mid, 1.38);
+            if (cost(full / 2, 1.55) < best) kc = full / 2, best = cost(full / 2, 1.55);
+            if (big && cost(big, 0.93) < best) kc = big, best = cost(big, 0.93);
         }
-        if (!bsk::valid_chunk_backward_f32(block, kc) && !(mid && kc == mid))
+        if (!bsk::valid_chunk_backward_f32(block, kc) && !(mid && kc == mid) && !(big && kc == big))
             return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     } else if (r->prec == BSK_FP64) {
         // one pass of up to 16 orders with the start mode as a constant where the

@@ -205,6 +205,7 @@ bool valid_chunk_backward_f32(int block, int kc);
 // other lane counts).
 int mid_chunk_forward_f32(int block);
 int mid_chunk_backward_f32(int block);
+int big_chunk_backward_f32(int block);   // 0: none for this lane count
 int chunk_forward_f32(int block);
 int chunk_forward_f64(int block);
 int onepass_chunk_forward_f64(int block);   // 0: none for this lane count

@@ -223,6 +223,10 @@ bool valid_chunk_backward_f32(int block, int kc)
 // passes instead of three (or two padded ones of 16).
 int mid_chunk_forward_f32(int block) { return block == 256 ? 12 : 0; }
 int mid_chunk_backward_f32(int block) { return block == 256 ? 12 : 0; }
+// A 24-order adjoint pass for 256-lane strips (two workgroups per CU, 239
+// VGPRs): 17 to 24 folded orders (N from 33 to 48) then take one pass instead
+// of two padded ones of 16 (16 x 1024^2, N = 43: 1.67 -> 1.16 ms).
+int big_chunk_backward_f32(int block) { return block == 256 ? 24 : 0; }
 int chunk_forward_f32(int block) { return kr_f32(block); }
 int chunk_forward_f64(int block) { return kr_f64(block); }
 int chunk_train_f32(int block) { return kr_train(block); }
@@ -362,7 +366,8 @@ hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s
 {
     // (a 12-order pass measured 6% slower than three of 8 on 22 orders at 1024^2,
     // and one 16-order pass at two workgroups per CU 3% slower than two of 8 on
-    // 16 orders at 4096^2)
+    // 16 orders at 4096^2, and one 24-order pass 14% slower than three of 8 on 22
+    // orders at 16 x 1024^2)
     if (kc != kr_train(block)) return hipErrorInvalidValue;
     switch (block) {
     case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3>(a, s, occ);
@@ -391,6 +396,7 @@ static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
     if (kc == KR) return bwd<BLOCK, KR, KL, 0>(a, s, occ);
     if constexpr (BLOCK == 256) {
         if (kc == mid_chunk_backward_f32(256)) return bwd<256, 12, 4, 3>(a, s, occ);
+        if (kc == big_chunk_backward_f32(256)) return bwd<256, 24, 4, 2>(a, s, occ);
     }
     // the half pass of 256 lanes fits three workgroups per compute unit
     return bwd<BLOCK, KR / 2, (KL < KR / 2 ? KL : KR / 2), BLOCK == 256 ? 3 : 0>(a, s, occ);
@@ -477,7 +483,9 @@ hipError_t launch_phase_table(const SpatialPlan &sp, int n, float *tab, hipStrea
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ)
 {
-    if (!valid_chunk_backward_f32(block, kc) && kc != mid_chunk_backward_f32(block)) return hipErrorInvalidValue;
+    if (!valid_chunk_backward_f32(block, kc) && kc != mid_chunk_backward_f32(block) &&
+        kc != big_chunk_backward_f32(block))
+        return hipErrorInvalidValue;
     hipError_t e;
     switch (block) {
     case 256: e = bwd_block<256>(a, kc, s, occ); break;

@@ -118,12 +118,14 @@ def test_rect4096_adjoint_sampled():
     assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref))
 
 
-def test_multi_pass_adjoint():
-    """N = 117: 59 folded orders, several passes in both training forward and adjoint."""
+@pytest.mark.parametrize("N,sigma", [(117, 15.0), (90, 17.0)])
+def test_multi_pass_adjoint(N, sigma):
+    """Several passes in both training forward and adjoint: N = 117 (59 folded orders,
+    adjoint passes of 16) and N = 90 (46 orders, two adjoint passes of 24)."""
     f = wl.rect_image(48, 80, seed=11, n_rect=8)
     g = np.random.default_rng(11).normal(size=f.shape)
-    gf_ref, gs_ref, _ = oracle.bilateral_grad(f.astype(np.float64), g, 4, 15.0, 117)
-    gi, gs = bilateral_backward(_cuda(f), _cuda(g), 4, 15.0, T, 117)
+    gf_ref, gs_ref, _ = oracle.bilateral_grad(f.astype(np.float64), g, 4, sigma, N)
+    gi, gs = bilateral_backward(_cuda(f), _cuda(g), 4, sigma, T, N)
     torch.cuda.synchronize()
     assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * np.max(np.abs(gf_ref))
     assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
