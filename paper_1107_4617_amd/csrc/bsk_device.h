@@ -740,6 +740,16 @@ constexpr int strip_lds_elems()
 // Exclusive prefix sums over aligned groups of CH consecutive lanes (CH a power
 // of two, at most 64); wch is the lane's index in its group.  Groups of 16 are
 // DPP rows: four shifted adds within the row and one final shift, no LDS.
+// Lane l - N of the same 16-lane DPP row (zero for the row's first N lanes);
+// N = 0 is the lane itself.
+template <int N>
+__device__ __forceinline__ float dpp_row_shr(float x)
+{
+    static_assert(N >= 0 && N <= 15, "row_shr reaches 15 lanes");
+    if constexpr (N == 0) return x;
+    else return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + N, 0xf, 0xf, true));
+}
+
 // A DPP lane move of a 64-bit value: both 32-bit halves with the same control;
 // lanes that the control leaves without a source (or rows outside row_mask)
 // read zero.
@@ -815,8 +825,16 @@ __device__ __forceinline__ AT group_exclusive_scan(AT x, int wch)
 // shift identity along the row: VQ, VQ cos(nu_j x) and VQ sin(nu_j x) are
 // prefix-summed, and the R stage forms
 // u0 Box[VQ] + sum_j u_j (cos(nu_j x) Box[VQ cos] + sin(nu_j x) Box[VQ sin]).
+//
+// RHC > 0 fixes the horizontal radius at compile time (rh == RHC).  The
+// one-pass plain FP32 forward then has its walkers hand out box sums rather
+// than prefix sums: a walker holds the prefixes E of its G positions in
+// registers, and E(p - 2 rh - 1) lies a fixed number of walkers to the left in
+// the same DPP row (the shift and the element index follow from 2 rh + 1 and
+// G), so each box sum Box(p) = E(p) - E(p - 2 rh - 1) costs one DPP-shifted
+// subtraction and the R stage reads one value per channel instead of two.
 template <typename AT, int BLOCK, int KR, int KL, class POL, int QUANT, bool KAHAN, int NSC = 0,
-          bool SEVEN = true>
+          bool SEVEN = true, int RHC = 0>
 __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, int by, AT *lds,
                                            double *red_lds, double *red_out)
 {
@@ -841,7 +859,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                   "the spatial kernel runs the plain FP32 forward");
 
     const int t = threadIdx.x;
-    const int H = gm.H, W = gm.W, rh = gm.rh, rv = gm.rv;
+    const int H = gm.H, W = gm.W, rh = RHC > 0 ? RHC : gm.rh, rv = gm.rv;
     const int Wt = BLOCK - 2 * rh;
     const int j0 = bx * Wt;
     const int jx = j0 - rh + t;
@@ -1067,6 +1085,9 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 constexpr bool JOINT = NSC == 0 && IsForward32<POL>::value && POL::START >= 0 && QUANT == 0 &&
                                        !KAHAN;
                 constexpr int NRD = JOINT ? KL * NPAIR : 1;
+                // walkers that produce box sums: one DPP row per LDS row, and the
+                // source walker at most 15 lanes to the left
+                constexpr bool WBOX = JOINT && RHC > 0 && CH == 16 && (2 * RHC + 1) / G + 1 <= 15;
                 V2 rhi[NRD], rlo[NRD];
                 AT loc[G];
                 if constexpr (JOINT) {
@@ -1074,7 +1095,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
 #pragma unroll
                         for (int q = 0; q < NRD; ++q) {
                             rhi[q] = VbR[q * RS + phi];
-                            rlo[q] = VbR[q * RS + plo];
+                            if constexpr (!WBOX) rlo[q] = VbR[q * RS + plo];
                         }
                     }
                     // Read whether or not the H stage runs this interval (every lane of
@@ -1103,7 +1124,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         for (int p = 0; p < NPAIR; ++p) {
                             // pair-row of channels (2p, 2p + 1), horizontal basis function b
                             const V2 *prow = VbR + (k * NPAIR + p) * NB * RS;
-                            if constexpr (JOINT) {
+                            if constexpr (WBOX) {
+                                // the box sums themselves, stored at position phi
+                                B[2 * p] = rhi[k * NPAIR + p].x;
+                                B[2 * p + 1] = rhi[k * NPAIR + p].y;
+                            } else if constexpr (JOINT) {
                                 const V2 hi = rhi[k * NPAIR + p], lo = rlo[k * NPAIR + p];
                                 B[2 * p] = hi.x - lo.x;
                                 B[2 * p + 1] = hi.y - lo.y;
@@ -1174,9 +1199,27 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                             // the prefixes of order m scaled by its weight v_m
                             const AT vw = vH[floormod(h - 1, NSUB)];
                             const AT offv = off * vw;
-                            VbH[wbase] = offv;
+                            if constexpr (WBOX) {
+                                // position p = G w + u: E(p - D), D = 2 rh + 1, is element
+                                // u - D mod G of walker w - QS (u >= DR) or of walker
+                                // w - QS - 1 (u < DR); positions below D (no output
+                                // reads them) take a zero from the DPP bound control
+                                constexpr int D = 2 * RHC + 1, QS = D / G, DR = D % G;
+                                AT E[G];
+                                E[0] = offv;
 #pragma unroll
-                            for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = fmat(loc[u], vw, offv);
+                                for (int u = 1; u < G; ++u) E[u] = fmat(loc[u], vw, offv);
+#pragma unroll
+                                for (int u = 0; u < G; ++u) {
+                                    const AT lo = u >= DR ? dpp_row_shr<QS>(E[u >= DR ? u - DR : 0])
+                                                          : dpp_row_shr<QS + 1>(E[u < DR ? u - DR + G : 0]);
+                                    VbH[wbase + 2 * u] = E[u] - lo;
+                                }
+                            } else {
+                                VbH[wbase] = offv;
+#pragma unroll
+                                for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = fmat(loc[u], vw, offv);
+                            }
                         } else {
                             VbH[wbase] = off;
 #pragma unroll

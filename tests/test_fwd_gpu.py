@@ -105,6 +105,19 @@ def test_shapes_and_edge_cases(shape, r, N, sigma, block, strip_h):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
+@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+@pytest.mark.parametrize("N,sigma", [(30, 30.0),    # 16 orders, even N: the full pass
+                                     (31, 30.0),    # 16 orders, odd N
+                                     (7, 70.0)])    # 4 orders, odd N: the half pass
+def test_compile_time_radius_kernels(r, N, sigma):
+    """The radii with their own one-pass kernels (the walkers hand out box sums): several
+    strips and segments with ragged tails, both start modes and both pass sizes."""
+    f = wl.rect_image(150, 700, seed=r + N, n_rect=12)
+    ref = oracle.bilateral(f, r, sigma, N)
+    out = _gpu_filter(f, r, sigma, N=N, strip_h=37)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
 @pytest.mark.parametrize("kc", [8, 12, 16])
 def test_every_pass_size(kc):
     """30 folded orders (N = 59) in passes of 8, 12 or 16 orders (4, 3 or 2 passes, the last
