@@ -41,9 +41,9 @@ BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy) and
 # SQ_INSTS_VALU (profiles/strip_kernel_fwd_rect4096_r20_s30.md).  Valid for this
 # kernel build only: set to None when the kernel changes.
-HEADLINE_KERNEL = "strip_kernel<float,256,16,4,PolForward<float,0>,0,false,3>"
-HEADLINE_HBM_BYTES = 283.2e6
-HEADLINE_VALU_INSTS = 201.62e6
+HEADLINE_KERNEL = "strip_kernel<float,256,16,4,PolForward<float,0>,0,false,3,20>"
+HEADLINE_HBM_BYTES = None
+HEADLINE_VALU_INSTS = None
 # VALU issue: one wave64 instruction per SIMD every 4 cycles (16 lanes, no
 # packed FP32), 4 SIMDs per CU, 256 CUs at 2.4 GHz
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4

@@ -883,9 +883,14 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     const int wch = t - wrow * CH;
     constexpr bool ALLWALK = ROWS * CH == BLOCK;
     const bool walker = ALLWALK || wrow < ROWS;
-    // row r of a buffer is member (r & 1) of pair-row r >> 1: element u of this
-    // walker's chunk sits at wbase + 2 u
-    const int wbase = (wrow >> 1) * (2 * RS) + 2 * (wch * G) + (wrow & 1);
+    // FP32: row r of a buffer is member (r & 1) of pair-row r >> 1, the two
+    // members interleaved (element u of this walker's chunk at wbase + 2 u).
+    // FP64 keeps every row contiguous (element u at wbase + u): interleaved
+    // 8-byte members would put walkers 8 apart on the same banks, while with
+    // G odd the walkers of a contiguous row start on distinct bank pairs.
+    constexpr bool PAIRED = sizeof(AT) == 4;
+    constexpr int WST = PAIRED ? 2 : 1;
+    const int wbase = PAIRED ? (wrow >> 1) * (2 * RS) + 2 * (wch * G) + (wrow & 1) : wrow * RS + wch * G;
     using V2 = typename Vec2<AT>::type;
     // box sum of output lane t: E(t + rh + 1) - E(t - rh)
     const int phi = t + rh + 1;
@@ -1105,7 +1110,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     // a register copy per element.
                     static_assert(!JOINT || ALLWALK, "joint reads assume every lane walks");
 #pragma unroll
-                    for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
+                    for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + WST * u];
                 }
                 // ---- R stage: box sums of the orders sR KL .. of row iR, recombined
                 if (actR && outlane) {
@@ -1132,10 +1137,15 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 const V2 hi = rhi[k * NPAIR + p], lo = rlo[k * NPAIR + p];
                                 B[2 * p] = hi.x - lo.x;
                                 B[2 * p + 1] = hi.y - lo.y;
-                            } else if constexpr (NSC == 0) {
+                            } else if constexpr (NSC == 0 && PAIRED) {
                                 const V2 hi = prow[phi], lo = prow[plo];
                                 B[2 * p] = hi.x - lo.x;
                                 B[2 * p + 1] = hi.y - lo.y;
+                            } else if constexpr (NSC == 0) {
+                                // contiguous rows 2 (k NPAIR + p) and the next one
+                                const AT *r0 = reinterpret_cast<const AT *>(VbR) + 2 * (k * NPAIR + p) * RS;
+                                B[2 * p] = r0[phi] - r0[plo];
+                                B[2 * p + 1] = r0[RS + phi] - r0[RS + plo];
                             } else {
                                 AT h0 = AT(0), h1 = AT(0);
                                 int b = 0;
@@ -1182,7 +1192,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     if (walker) {
                         if constexpr (!JOINT) {
 #pragma unroll
-                            for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + 2 * u];
+                            for (int u = 0; u < G; ++u) loc[u] = VbH[wbase + WST * u];
                         }
                         // local exclusive prefixes: loc[u] = sum_{v < u} of the chunk (loc[0] = 0 is implicit)
                         run = loc[0];
@@ -1213,17 +1223,17 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 for (int u = 0; u < G; ++u) {
                                     const AT lo = u >= DR ? dpp_row_shr<QS>(E[u >= DR ? u - DR : 0])
                                                           : dpp_row_shr<QS + 1>(E[u < DR ? u - DR + G : 0]);
-                                    VbH[wbase + 2 * u] = E[u] - lo;
+                                    VbH[wbase + WST * u] = E[u] - lo;
                                 }
                             } else {
                                 VbH[wbase] = offv;
 #pragma unroll
-                                for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = fmat(loc[u], vw, offv);
+                                for (int u = 1; u < G; ++u) VbH[wbase + WST * u] = fmat(loc[u], vw, offv);
                             }
                         } else {
                             VbH[wbase] = off;
 #pragma unroll
-                            for (int u = 1; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
+                            for (int u = 1; u < G; ++u) VbH[wbase + WST * u] = loc[u] + off;
                         }
                     }
                 }
@@ -1304,8 +1314,12 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
 #pragma unroll
                         for (int p = 0; p < NPAIR; ++p) {
                             V2 *prow = VbV + (k * NPAIR + p) * NB * RS + vpos;
-                            if constexpr (NSC == 0) {
+                            if constexpr (NSC == 0 && PAIRED) {
                                 prow[0] = Vec2<AT>::make(V[m][2 * p], V[m][2 * p + 1]);
+                            } else if constexpr (NSC == 0) {
+                                AT *r0 = reinterpret_cast<AT *>(VbV) + 2 * (k * NPAIR + p) * RS + vpos;
+                                r0[0] = V[m][2 * p];
+                                r0[RS] = V[m][2 * p + 1];
                             } else {
                                 // vertically weighted sums of the pair, then their horizontal basis rows
                                 AT vq[2];
