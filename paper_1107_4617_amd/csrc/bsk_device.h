@@ -1038,6 +1038,12 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
         }
         typename ChainOf<POL, AT>::type ci, co, cc;
         AT ki[NPAIR], ko[NPAIR], auxc[NAUX], acc[NACC];
+        // a later pass's partial accumulators of the R stage's row, read from the
+        // workspace when the row's R stage starts, added when it ends (NSUB
+        // intervals later), so the HBM latency is not waited out at the row's end
+        AT wsv[NACC];
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) wsv[q] = AT(0);
         // spatial kernel: kappa times the phases of the incoming and outgoing
         // rows, and u_j (cos, sin)(nu_j i) of the output row
         AT kic[NPAIR][NSCR], kis[NPAIR][NSCR], koc[NPAIR][NSCR], kos[NPAIR][NSCR];
@@ -1120,6 +1126,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         chain_start<POL>(cc, colok, auxc, om0, dlt, smode, om1, d1);
 #pragma unroll
                         for (int q = 0; q < NACC; ++q) acc[q] = AT(0);
+                        if (!first) {
+                            const long o = (long)iR * W + jx;
+#pragma unroll
+                            for (int q = 0; q < NACC; ++q) wsv[q] = ((const AT *)gm.ws)[q * plane + o];
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < KL; ++k) {
@@ -1358,7 +1369,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                     const long o = (long)iR * W + jx;
                     if (!first) {
 #pragma unroll
-                        for (int q = 0; q < NACC; ++q) acc[q] += ((AT *)gm.ws)[q * plane + o];
+                        for (int q = 0; q < NACC; ++q) acc[q] += wsv[q];
                     }
                     if (last) {
                         if constexpr (QUANT != 0 && IsForward32<POL>::value) {
