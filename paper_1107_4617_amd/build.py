@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsk.so")
-SOURCES = ["bsk_kernels.hip", "bsk_radius.hip", "bsk_batched.hip", "bsk_poly.hip", "bsk_noalloc.hip", "bsk_plan.cpp",
+SOURCES = ["bsk_kernels.hip", "bsk_radius.hip", "bsk_radius_grad.hip", "bsk_batched.hip", "bsk_poly.hip", "bsk_noalloc.hip", "bsk_plan.cpp",
            "bsk_api.cpp", "bsk_batched.cpp"]
 
 # Packed FP32 instructions are turned off in the device code; hipcc's host

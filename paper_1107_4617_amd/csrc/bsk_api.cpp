@@ -80,7 +80,7 @@ int get_ws(void *stream, int slot, size_t bytes, void **out, unsigned long long 
             // the previous buffer may still be read by queued work on this stream
             e = hipStreamSynchronize((hipStream_t)stream);
             if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            hipFree(b.ptr);
+            (void)hipFree(b.ptr);
             b.ptr = nullptr;
             b.bytes = 0;
         }
@@ -170,9 +170,11 @@ static int pick_chunk_poly(int pairs, int N, int full)
 static int kernel_occupancy(const Resolved &r, int kind)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, int, int>, int> cache;
+    static std::map<std::tuple<int, int, int, int, int, int, int, int>, int> cache;
+    // the radius picks the compile-time-radius kernels where they exist, whose
+    // register counts (and so residency) differ from the run-time-radius ones
     const auto key = std::make_tuple(kind + 3 * r.range_kernel, r.block, r.kc, r.prec, r.kahan,
-                                     r.sp.nsc * 2 + (r.sp.even ? 1 : 0), [] {
+                                     r.sp.nsc * 2 + (r.sp.even ? 1 : 0), r.rh, [] {
         int d = 0;
         (void)hipGetDevice(&d);
         return d;
@@ -184,6 +186,7 @@ static int kernel_occupancy(const Resolved &r, int kind)
     }
     bsk::StripArgs a;
     std::memset(&a, 0, sizeof(a));
+    a.rh = r.rh;
     int occ = 1;
     if (kind == kPatch2) {
         (void)bsk::launch_patch2_f32(a, r.block, r.kc, 0, nullptr, &occ);

@@ -337,7 +337,7 @@ int stage_upload(void *stream, const std::vector<char> &tab, void *dev_dst)
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
     if (s.bytes < tab.size()) {
-        if (s.host) hipHostFree(s.host);
+        if (s.host) (void)hipHostFree(s.host);
         s.host = nullptr;
         s.bytes = 0;
         e = hipHostMalloc(&s.host, tab.size(), hipHostMallocDefault);
@@ -391,10 +391,10 @@ bool same_descs(const GraphEntry &g, const bsk_image_desc *d, int B, float T, co
 
 void free_graph(GraphEntry &g)
 {
-    if (g.exec) hipGraphExecDestroy(g.exec);
-    if (g.graph) hipGraphDestroy(g.graph);
-    if (g.tab) hipFree(g.tab);
-    if (g.ws) hipFree(g.ws);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.tab) (void)hipFree(g.tab);
+    if (g.ws) (void)hipFree(g.ws);
     g.exec = nullptr;
     g.graph = nullptr;
     g.tab = nullptr;
@@ -659,10 +659,10 @@ void bsk_release_batched(void)
     std::lock_guard<std::mutex> lk(g_stage_mu);
     for (auto &kv : g_stage) {
         if (kv.second.done) {
-            hipEventSynchronize(kv.second.done);
-            hipEventDestroy(kv.second.done);
+            (void)hipEventSynchronize(kv.second.done);
+            (void)hipEventDestroy(kv.second.done);
         }
-        if (kv.second.host) hipHostFree(kv.second.host);
+        if (kv.second.host) (void)hipHostFree(kv.second.host);
     }
     g_stage.clear();
 }
@@ -719,20 +719,20 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
                     if (hipEventRecord(e1, (hipStream_t)stream) != hipSuccess) break;
                     if (hipEventSynchronize(e1) != hipSuccess) break;
                     float ms = 0.f;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
                     if (rep > 0 && ms < ms_min) ms_min = ms;   // first run is a warm-up
                 }
                 if (st) {
-                    hipEventDestroy(e0);
-                    hipEventDestroy(e1);
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
                     return st;
                 }
                 if (ms_min < best.ms) best = TuneVal{b, S, c.order_chunk, (double)ms_min};
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (best.block == 0) return fail(BSK_EUNSUPPORTED, "no launch shape fits this request");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -783,7 +783,7 @@ int bsk_autotune_batched(const bsk_image_desc *descs, int B, float T, const bsk_
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(BSK_EHIP, "hipEventCreate failed");
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return fail(BSK_EHIP, "hipEventCreate failed");
     }
     // one warm-up launch, then the fastest of three
@@ -798,7 +798,8 @@ int bsk_autotune_batched(const bsk_image_desc *descs, int B, float T, const bsk_
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
             float t = 0.f;
-            hipEventElapsedTime(&t, e0, e1);
+            e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
             if (rep > 0 && t < best) best = t;
         }
         *ms = best;
@@ -863,8 +864,8 @@ int bsk_autotune_batched(const bsk_image_desc *descs, int B, float T, const bsk_
         }
         if (keep.first) ovr.shape[key] = keep;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st) return st;
     // the lanes and the buckets' shapes the sweep settled on (buckets it left
     // at the defaults record nothing), stored for later calls and written to `path`

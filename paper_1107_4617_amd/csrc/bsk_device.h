@@ -1098,7 +1098,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 constexpr int NRD = JOINT ? KL * NPAIR : 1;
                 // walkers that produce box sums: one DPP row per LDS row, and the
                 // source walker at most 15 lanes to the left
-                constexpr bool WBOX = JOINT && RHC > 0 && CH == 16 && (2 * RHC + 1) / G + 1 <= 15;
+                constexpr bool WBOX = RHC > 0 && NSC == 0 && PAIRED && FOLDV && CH == 16 &&
+                                      (2 * RHC + 1) / G + 1 <= 15;
                 V2 rhi[NRD], rlo[NRD];
                 AT loc[G];
                 if constexpr (JOINT) {
@@ -1140,14 +1141,19 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         for (int p = 0; p < NPAIR; ++p) {
                             // pair-row of channels (2p, 2p + 1), horizontal basis function b
                             const V2 *prow = VbR + (k * NPAIR + p) * NB * RS;
-                            if constexpr (WBOX) {
-                                // the box sums themselves, stored at position phi
+                            if constexpr (WBOX && JOINT) {
+                                // the box sums themselves, read at position phi after the barrier
                                 B[2 * p] = rhi[k * NPAIR + p].x;
                                 B[2 * p + 1] = rhi[k * NPAIR + p].y;
                             } else if constexpr (JOINT) {
                                 const V2 hi = rhi[k * NPAIR + p], lo = rlo[k * NPAIR + p];
                                 B[2 * p] = hi.x - lo.x;
                                 B[2 * p + 1] = hi.y - lo.y;
+                            } else if constexpr (WBOX) {
+                                // the box sums themselves, stored at position phi
+                                const V2 hi = prow[phi];
+                                B[2 * p] = hi.x;
+                                B[2 * p + 1] = hi.y;
                             } else if constexpr (NSC == 0 && PAIRED) {
                                 const V2 hi = prow[phi], lo = prow[plo];
                                 B[2 * p] = hi.x - lo.x;

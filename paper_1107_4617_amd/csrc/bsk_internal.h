@@ -183,6 +183,12 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, int kc, hipStream_t
 // (kc the full or the half 256-lane pass, K <= kc, start mode 0 or 1).
 bool forward_radius_kernel(int block, int rh);
 hipError_t launch_forward_f32_radius(const StripArgs &a, int kc, hipStream_t s, int *occ = nullptr);
+// The training forward (8-order pass) and the adjoint (24-, 16- and 8-order
+// passes) with the same compile-time radii (bsk_radius_grad.hip).
+bool train_radius_kernel(int block, int rh);
+bool backward_radius_kernel(int block, int rh, int kc);
+hipError_t launch_train_f32_radius(const StripArgs &a, hipStream_t s, int *occ = nullptr);
+hipError_t launch_backward_f32_radius(const StripArgs &a, int kc, hipStream_t s, int *occ = nullptr);
 hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *grad_sigma, double inv_sigma,
                                int nred, hipStream_t s, int *occ = nullptr);

@@ -38,21 +38,6 @@ __global__ void __launch_bounds__(256) phase_table_kernel(int n, int nsc, double
     tab[2 * idx + 1] = (float)sin(ang);
 }
 
-template <int BLOCK, int KR, int KL, int MINB = 0>
-__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
-    backward_kernel(const StripArgs a)
-{
-    __shared__ __align__(16) float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
-    __shared__ double red_lds[BLOCK];
-    int bx, by, b;
-    if (!stack_tile(a, &bx, &by, &b)) return;
-    const IO io = stack_io(a, b);
-    const Geom gm = stack_geom(a, b);
-    // one partial sum per tile of the whole stack, image-major like the tiles
-    const long segs = (a.io.H + a.S - 1) / a.S;
-    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false>(io, gm, bx, by, lds, red_lds,
-                                                            a.red + (((long)b * segs + by) * a.strips + bx));
-}
 
 // Fixed-order sum of the per-workgroup partials: grad_sigma = -(1/sigma) sum.
 __global__ void __launch_bounds__(256) sigma_reduce_kernel(const float *unused, const double *part, int n,
@@ -109,7 +94,7 @@ static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *oc
         if (a.K <= kc && (a.start_mode == 0 || a.start_mode == 1)) {
             // the plain stack at a radius with its own kernels
             if constexpr (QUANT == 0 && !KAHAN) {
-                if (!occ && (kc == KR || kc == KR / 2) && forward_radius_kernel(BLOCK, a.rh))
+                if ((kc == KR || kc == KR / 2) && forward_radius_kernel(BLOCK, a.rh))
                     return launch_forward_f32_radius(a, kc, s, occ);
             }
             if (kc == KR)
@@ -231,6 +216,7 @@ hipError_t launch_forward_f64(const StripArgs &a, int block, int kc, hipStream_t
 
 hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
+    if (kc == kr_train(block) && train_radius_kernel(block, a.rh)) return launch_train_f32_radius(a, s, occ);
     // (a 12-order pass measured 6% slower than three of 8 on 22 orders at 1024^2,
     // and one 16-order pass at two workgroups per CU 3% slower than two of 8 on
     // 16 orders at 4096^2, and one 24-order pass 14% slower than three of 8 on 22
@@ -244,22 +230,13 @@ hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s
     }
 }
 
-template <int BLOCK, int KR, int KL, int MINB>
-static hipError_t bwd(const StripArgs &a, hipStream_t s, int *occ)
-{
-    if (occ) return query_occupancy((const void *)backward_kernel<BLOCK, KR, KL, MINB>, BLOCK, occ);
-    const int Wt = BLOCK - 2 * a.rh;
-    if (Wt < 1) return hipErrorInvalidValue;
-    if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
-    const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
-    hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB>), grid, dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
-}
 
 template <int BLOCK>
 static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
     constexpr int KR = kr_bwd(BLOCK), KL = kl_bwd(BLOCK);
+    // a radius with its own kernels
+    if (backward_radius_kernel(BLOCK, a.rh, kc)) return launch_backward_f32_radius(a, kc, s, occ);
     if (kc == KR) return bwd<BLOCK, KR, KL, 0>(a, s, occ);
     if constexpr (BLOCK == 256) {
         if (kc == mid_chunk_backward_f32(256)) return bwd<256, 12, 4, 3>(a, s, occ);

@@ -1,0 +1,71 @@
+// Training forward and adjoint (256 lanes) with the box radius as a
+// compile-time constant, for the radii that have compile-time-radius forward
+// kernels (bsk_radius.hip).  Their walkers hand box sums to the R stage, which
+// then reads one value per channel instead of two: the training forward's R
+// stage reads six channels per order and the adjoint's four, so both gain more
+// than the forward.  Other radii use the run-time-radius kernels.
+#include "bsk_strip.h"
+
+namespace bsk {
+
+namespace {
+
+template <int R>
+hipError_t train_radius(const StripArgs &a, hipStream_t s, int *occ)
+{
+    return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3, R>(a, s, occ);
+}
+
+// the pass shapes of bwd_block<256>: the 24- and 16-order passes at two
+// workgroups per CU, the 8-order half pass at three
+template <int R>
+hipError_t backward_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
+{
+    switch (kc) {
+    case 24: return bwd<256, 24, 4, 2, R>(a, s, occ);
+    case 16: return bwd<256, 16, 4, 0, R>(a, s, occ);
+    case 8: return bwd<256, 8, 4, 3, R>(a, s, occ);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool train_radius_kernel(int block, int rh) { return forward_radius_kernel(block, rh); }
+
+bool backward_radius_kernel(int block, int rh, int kc)
+{
+    return forward_radius_kernel(block, rh) && (kc == 24 || kc == 16 || kc == 8);
+}
+
+hipError_t launch_train_f32_radius(const StripArgs &a, hipStream_t s, int *occ)
+{
+    switch (a.rh) {
+    case 3: return train_radius<3>(a, s, occ);
+    case 5: return train_radius<5>(a, s, occ);
+    case 8: return train_radius<8>(a, s, occ);
+    case 10: return train_radius<10>(a, s, occ);
+    case 16: return train_radius<16>(a, s, occ);
+    case 20: return train_radius<20>(a, s, occ);
+    case 25: return train_radius<25>(a, s, occ);
+    case 32: return train_radius<32>(a, s, occ);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backward_f32_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
+{
+    switch (a.rh) {
+    case 3: return backward_radius<3>(a, kc, s, occ);
+    case 5: return backward_radius<5>(a, kc, s, occ);
+    case 8: return backward_radius<8>(a, kc, s, occ);
+    case 10: return backward_radius<10>(a, kc, s, occ);
+    case 16: return backward_radius<16>(a, kc, s, occ);
+    case 20: return backward_radius<20>(a, kc, s, occ);
+    case 25: return backward_radius<25>(a, kc, s, occ);
+    case 32: return backward_radius<32>(a, kc, s, occ);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bsk

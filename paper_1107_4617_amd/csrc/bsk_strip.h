@@ -1,5 +1,6 @@
-// The single-image strip kernel and its launch helper, shared by the launch
-// files (bsk_kernels.hip, bsk_radius.hip).  The kernel body and its design
+// The strip kernels (single image, image stacks, adjoint) and their launch
+// helpers, shared by the launch files (bsk_kernels.hip, bsk_radius.hip,
+// bsk_radius_grad.hip).  The kernel body and its design
 // are in bsk_device.h.
 #pragma once
 #include "bsk_device.h"
@@ -116,12 +117,29 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, K
         if (!stack_tile(a, &bx, &by, &b)) return;
         const IO io = stack_io(a, b);
         const Geom gm = stack_geom(a, b);
-        strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN>(io, gm, bx, by, lds, nullptr, nullptr);
+        strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, 0, true, RHC>(io, gm, bx, by, lds, nullptr, nullptr);
     } else {
         if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
         const Geom gm = geom_of(a);
         strip_body<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, 0, true, RHC>(a.io, gm, bx, by, lds, nullptr, nullptr);
     }
+}
+
+// The adjoint over a stack of images; RHC as for strip_kernel.
+template <int BLOCK, int KR, int KL, int MINB = 0, int RHC = 0>
+__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
+    backward_kernel(const StripArgs a)
+{
+    __shared__ __align__(16) float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
+    __shared__ double red_lds[BLOCK];
+    int bx, by, b;
+    if (!stack_tile(a, &bx, &by, &b)) return;
+    const IO io = stack_io(a, b);
+    const Geom gm = stack_geom(a, b);
+    // one partial sum per tile of the whole stack, image-major like the tiles
+    const long segs = (a.io.H + a.S - 1) / a.S;
+    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false, 0, true, RHC>(
+        io, gm, bx, by, lds, red_lds, a.red + (((long)b * segs + by) * a.strips + bx));
 }
 
 // ---------------------------------------------------------------- launches --
@@ -146,6 +164,19 @@ static hipError_t launch(const StripArgs &a, hipStream_t s, int *occ)
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
     const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
     hipLaunchKernelGGL((strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB, RHC>), grid, dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int BLOCK, int KR, int KL, int MINB, int RHC = 0>
+static hipError_t bwd(const StripArgs &a, hipStream_t s, int *occ)
+{
+    if (occ) return query_occupancy((const void *)backward_kernel<BLOCK, KR, KL, MINB, RHC>, BLOCK, occ);
+    if (RHC > 0 && a.rh != RHC) return hipErrorInvalidValue;
+    const int Wt = BLOCK - 2 * a.rh;
+    if (Wt < 1) return hipErrorInvalidValue;
+    if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
+    const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
+    hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB, RHC>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

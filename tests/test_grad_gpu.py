@@ -118,6 +118,26 @@ def test_rect4096_adjoint_sampled():
     assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+@pytest.mark.parametrize("N,sigma", [(30, 30.0),    # 16 orders: two training passes of 8, one adjoint pass of 16
+                                     (43, 25.0),    # 22 orders: three training passes, one adjoint pass of 24
+                                     (7, 70.0)])    # 4 orders: one training pass, the adjoint's half pass
+def test_compile_time_radius_gradients(r, N, sigma):
+    """The radii with their own training-forward and adjoint kernels (the walkers hand out box
+    sums), across two strips and several segments: output, saved normaliser and both gradients
+    against the oracle."""
+    f = wl.rect_image(40, 260, seed=r + N, n_rect=8)
+    g = np.random.default_rng(r + N).normal(size=f.shape)
+    gf_ref, gs_ref, u_ref = oracle.bilateral_grad(f.astype(np.float64), g, r, sigma, N)
+    x = _cuda(f)
+    out, saved = bilateral_train(x, r, sigma, T, N)
+    assert np.max(np.abs(out.cpu().numpy() - u_ref)) <= 1e-4 * T
+    gi, gs = bilateral_backward(x, _cuda(g), r, sigma, T, N, out=out, saved=saved)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * np.max(np.abs(gf_ref))
+    assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
+
+
 @pytest.mark.parametrize("N,sigma", [(117, 15.0), (90, 17.0)])
 def test_multi_pass_adjoint(N, sigma):
     """Several passes in both training forward and adjoint: N = 117 (59 folded orders,
