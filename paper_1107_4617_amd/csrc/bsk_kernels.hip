@@ -88,15 +88,15 @@ static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *oc
     constexpr int KR = kr_f32(BLOCK), KL = kl_f32(BLOCK);
     // three workgroups per compute unit where the registers allow it
     constexpr int MINB = (BLOCK == 256 && !KAHAN) ? 3 : 0;
+    if constexpr (BLOCK == 256 && QUANT == 0 && !KAHAN) {
+        // the plain stack at a radius with its own kernels
+        if ((kc == KR || kc == KR / 2) && forward_radius_kernel(BLOCK, a.rh))
+            return launch_forward_f32_radius(a, kc, s, occ);
+    }
     if constexpr (BLOCK == 256) {
         // one pass: the chain start mode as a constant (both pass sizes for the
         // plain FP32 stack, the full pass for the 16-bit and compensated ones)
         if (a.K <= kc && (a.start_mode == 0 || a.start_mode == 1)) {
-            // the plain stack at a radius with its own kernels
-            if constexpr (QUANT == 0 && !KAHAN) {
-                if ((kc == KR || kc == KR / 2) && forward_radius_kernel(BLOCK, a.rh))
-                    return launch_forward_f32_radius(a, kc, s, occ);
-            }
             if (kc == KR)
                 return a.start_mode == 0
                            ? launch<float, BLOCK, KR, KL, PolForward<float, 0>, QUANT, KAHAN, MINB>(a, s, occ)
@@ -116,6 +116,7 @@ static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *oc
 static hipError_t fwd32_mid(const StripArgs &a, hipStream_t s, int *occ)
 {
     constexpr int KR = 12, KL = 4;
+    if (forward_radius_kernel(256, a.rh)) return launch_forward_f32_radius(a, KR, s, occ);
     if (a.K <= KR && (a.start_mode == 0 || a.start_mode == 1))
         return a.start_mode == 0 ? launch<float, 256, KR, KL, PolForward<float, 0>, 0, false, 3>(a, s, occ)
                                  : launch<float, 256, KR, KL, PolForward<float, 1>, 0, false, 3>(a, s, occ);

@@ -1,23 +1,35 @@
-// One-pass plain FP32 forward (256 lanes, the full and the half pass) with
-// the box radius as a compile-time constant, for a set of common radii.  Its
-// walkers hand box sums to the R stage instead of prefix sums (strip_body,
-// RHC > 0), which halves the R stage's LDS reads.  Other radii, and every
-// other form, use the run-time-radius kernels of bsk_kernels.hip.
+// Plain FP32 forward (256 lanes, passes of 16, 12 or 8 orders, one pass or
+// several) with the box radius as a compile-time constant, for a set of
+// common radii.  Its walkers hand box sums to the R stage instead of prefix
+// sums (strip_body, RHC > 0), which halves the R stage's LDS reads.  Other
+// radii, and the 16-bit and compensated stacks, use the run-time-radius
+// kernels of bsk_kernels.hip.
 #include "bsk_strip.h"
 
 namespace bsk {
 
 namespace {
 
+template <int R, int KR>
+hipError_t fwd_radius_pass(const StripArgs &a, hipStream_t s, int *occ)
+{
+    constexpr int KL = kl_f32(256);
+    // one pass with the start mode as a constant, else passes with the run-time mode
+    if (a.K <= KR && a.start_mode == 0) return launch<float, 256, KR, KL, PolForward<float, 0>, 0, false, 3, R>(a, s, occ);
+    if (a.K <= KR && a.start_mode == 1) return launch<float, 256, KR, KL, PolForward<float, 1>, 0, false, 3, R>(a, s, occ);
+    return launch<float, 256, KR, KL, PolForward<float>, 0, false, 3, R>(a, s, occ);
+}
+
+// the three pass sizes of the 256-lane plain FP32 forward: 16, 12 and 8 orders
 template <int R>
 hipError_t fwd_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
-    constexpr int KR = kr_f32(256), KL = kl_f32(256);
-    if (kc == KR)
-        return a.start_mode == 0 ? launch<float, 256, KR, KL, PolForward<float, 0>, 0, false, 3, R>(a, s, occ)
-                                 : launch<float, 256, KR, KL, PolForward<float, 1>, 0, false, 3, R>(a, s, occ);
-    return a.start_mode == 0 ? launch<float, 256, KR / 2, KL, PolForward<float, 0>, 0, false, 3, R>(a, s, occ)
-                             : launch<float, 256, KR / 2, KL, PolForward<float, 1>, 0, false, 3, R>(a, s, occ);
+    switch (kc) {
+    case 16: return fwd_radius_pass<R, 16>(a, s, occ);
+    case 12: return fwd_radius_pass<R, 12>(a, s, occ);
+    case 8: return fwd_radius_pass<R, 8>(a, s, occ);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -33,8 +45,7 @@ bool forward_radius_kernel(int block, int rh)
 
 hipError_t launch_forward_f32_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
-    if ((kc != kr_f32(256) && kc != kr_f32(256) / 2) || a.K > kc || (a.start_mode != 0 && a.start_mode != 1))
-        return hipErrorInvalidValue;
+    static_assert(kr_f32(256) == 16 && kl_f32(256) == 4, "the pass sizes below are the 256-lane ones");
     switch (a.rh) {
     case 3: return fwd_radius<3>(a, kc, s, occ);
     case 5: return fwd_radius<5>(a, kc, s, occ);

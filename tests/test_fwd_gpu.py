@@ -118,6 +118,19 @@ def test_compile_time_radius_kernels(r, N, sigma):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
+@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+@pytest.mark.parametrize("N,sigma", [(20, 36.0),    # 11 orders: one 12-order pass
+                                     (43, 25.0),    # 22 orders: two 12-order passes
+                                     (117, 15.0)])  # 59 orders: four 16-order passes
+def test_compile_time_radius_kernels_multi_pass(r, N, sigma):
+    """The compile-time-radius kernels with the 12-order pass and with several passes
+    (run-time start mode, partial accumulators in the workspace)."""
+    f = wl.rect_image(80, 460, seed=3 * r + N, n_rect=10)
+    ref = oracle.bilateral(f, r, sigma, N)
+    out = _gpu_filter(f, r, sigma, N=N, strip_h=29)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
 @pytest.mark.parametrize("kc", [8, 12, 16])
 def test_every_pass_size(kc):
     """30 folded orders (N = 59) in passes of 8, 12 or 16 orders (4, 3 or 2 passes, the last
