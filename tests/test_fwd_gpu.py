@@ -96,6 +96,11 @@ def test_fp64_matches_oracle(shape, r, N, sigma, block):
     ((90, 300), 6, 43, 25.0, 256, 0),       # 22 orders, two 12-order passes
     ((40, 1100), 200, 30, 30.0, 1024, 0),   # 1024-lane strips
     ((12, 1100), 500, 30, 30.0, 0, 0),      # the largest clamped radius (BSK_MAX_RADIUS)
+    # compile-time-radius kernels on images smaller than their window
+    ((1, 1), 20, 30, 30.0, 0, 0),
+    ((3, 50), 32, 30, 30.0, 0, 0),
+    ((60, 2), 16, 43, 25.0, 0, 0),          # two 12-order passes
+    ((33, 217), 20, 30, 30.0, 0, 5),        # one column past a full strip, 5-row segments
 ])
 def test_shapes_and_edge_cases(shape, r, N, sigma, block, strip_h):
     """Orders at or above N_0(sigma_r, 255), where the kernel is a valid (non-negative) kernel."""

@@ -138,6 +138,21 @@ def test_compile_time_radius_gradients(r, N, sigma):
     assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
 
 
+@pytest.mark.parametrize("shape,r", [((1, 1), 20), ((5, 40), 32), ((50, 3), 10)])
+def test_compile_time_radius_gradients_small_images(shape, r):
+    """Compile-time-radius training forward and adjoint on images smaller than the window."""
+    f = wl.rect_image(*shape, seed=sum(shape) + r, n_rect=3)
+    g = np.random.default_rng(r).normal(size=f.shape)
+    gf_ref, gs_ref, u_ref = oracle.bilateral_grad(f.astype(np.float64), g, r, 25.0, 43)
+    x = _cuda(f)
+    out, saved = bilateral_train(x, r, 25.0, T, 43)
+    assert np.max(np.abs(out.cpu().numpy() - u_ref)) <= 1e-4 * T
+    gi, gs = bilateral_backward(x, _cuda(g), r, 25.0, T, 43, out=out, saved=saved)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * max(np.max(np.abs(gf_ref)), 1e-12)
+    assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref) + 1e-9
+
+
 @pytest.mark.parametrize("N,sigma", [(117, 15.0), (90, 17.0)])
 def test_multi_pass_adjoint(N, sigma):
     """Several passes in both training forward and adjoint: N = 117 (59 folded orders,
