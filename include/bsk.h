@@ -139,6 +139,10 @@ typedef struct {
  *   sigma_r > 0: range scale (the Gaussian limit's standard deviation)
  *   T > 0:  range bound, selects N_0
  * Runs on the default stream and synchronises before returning.
+ * Performance: with 256-lane strips the radii 3, 5, 8, 10, 16, 20, 25 and 32
+ * run kernels compiled for that radius (the plain FP32 forward, and the
+ * training forward and adjoint below), 4-9% faster than the run-time-radius
+ * kernels every other radius uses; the results agree to FP32 rounding.
  */
 int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_r, float T,
                         float *out);
