@@ -1098,8 +1098,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                 constexpr int NRD = JOINT ? KL * NPAIR : 1;
                 // walkers that produce box sums: one DPP row per LDS row, and the
                 // source walker at most 15 lanes to the left
-                constexpr bool WBOX = RHC > 0 && NSC == 0 && PAIRED && FOLDV && CH == 16 &&
-                                      (2 * RHC + 1) / G + 1 <= 15;
+                constexpr bool WBOX = RHC > 0 && PAIRED && FOLDV && CH == 16 && (2 * RHC + 1) / G + 1 <= 15;
                 V2 rhi[NRD], rlo[NRD];
                 AT loc[G];
                 if constexpr (JOINT) {
@@ -1149,7 +1148,7 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 const V2 hi = rhi[k * NPAIR + p], lo = rlo[k * NPAIR + p];
                                 B[2 * p] = hi.x - lo.x;
                                 B[2 * p + 1] = hi.y - lo.y;
-                            } else if constexpr (WBOX) {
+                            } else if constexpr (WBOX && NSC == 0) {
                                 // the box sums themselves, stored at position phi
                                 const V2 hi = prow[phi];
                                 B[2 * p] = hi.x;
@@ -1164,21 +1163,30 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 B[2 * p] = r0[phi] - r0[plo];
                                 B[2 * p + 1] = r0[RS + phi] - r0[RS + plo];
                             } else {
+                                // box sums of a basis row pair: from two prefixes, or the
+                                // walkers' box sum itself
+                                auto box = [&](const V2 *row) {
+                                    if constexpr (WBOX) {
+                                        return row[phi];
+                                    } else {
+                                        const V2 hi = row[phi], lo = row[plo];
+                                        return Vec2<AT>::make(hi.x - lo.x, hi.y - lo.y);
+                                    }
+                                };
                                 AT h0 = AT(0), h1 = AT(0);
                                 int b = 0;
                                 if constexpr (SEVEN) {
-                                    const V2 hi = prow[phi], lo = prow[plo];
-                                    h0 = u0 * (hi.x - lo.x);
-                                    h1 = u0 * (hi.y - lo.y);
+                                    const V2 bz = box(prow);
+                                    h0 = u0 * bz.x;
+                                    h1 = u0 * bz.y;
                                     b = 1;
                                 }
 #pragma unroll
                                 for (int j = 0; j < NSC; ++j) {
                                     const V2 *rc_ = prow + (b + 2 * j) * RS;
-                                    const V2 *rs_ = rc_ + RS;
-                                    const V2 ch = rc_[phi], cl = rc_[plo], sh = rs_[phi], sl = rs_[plo];
-                                    h0 = fmat(rsw[j], sh.x - sl.x, fmat(rcw[j], ch.x - cl.x, h0));
-                                    h1 = fmat(rsw[j], sh.y - sl.y, fmat(rcw[j], ch.y - cl.y, h1));
+                                    const V2 bc = box(rc_), bs = box(rc_ + RS);
+                                    h0 = fmat(rsw[j], bs.x, fmat(rcw[j], bc.x, h0));
+                                    h1 = fmat(rsw[j], bs.y, fmat(rcw[j], bc.y, h1));
                                 }
                                 B[2 * p] = h0;
                                 B[2 * p + 1] = h1;

@@ -12,15 +12,16 @@ constexpr int spatial_minb()
 {
     return lds_occupancy(strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>() * 4) >= 2 ? 2 : 1;
 }
-template <int BLOCK, int KR, int NSC, bool SEVEN>
+// RHC as for strip_kernel.
+template <int BLOCK, int KR, int NSC, bool SEVEN, int RHC = 0>
 __global__ void __launch_bounds__(BLOCK, (spatial_minb<BLOCK, NSC, SEVEN>())) spatial_kernel(const StripArgs a)
 {
     __shared__ __align__(16) float lds[strip_lds_elems<PolForward<float>::NCH, 1, BLOCK, NSC, SEVEN>()];
     int bx, by;
     if (!xcd_tile(a.strips, (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
     const Geom gm = geom_of(a);
-    strip_body<float, BLOCK, KR, 1, PolForward<float>, 0, false, NSC, SEVEN>(a.io, gm, bx, by, lds, nullptr,
-                                                                             nullptr);
+    strip_body<float, BLOCK, KR, 1, PolForward<float>, 0, false, NSC, SEVEN, RHC>(a.io, gm, bx, by, lds, nullptr,
+                                                                                  nullptr);
 }
 
 // Phase table of the spatial kernel: (cos, sin)(nu_j y) for y < n, the angle
@@ -265,21 +266,45 @@ int chunk_spatial_small_f32(int block, int nsc)
 // 512-lane strips hold the LDS rows of at most two frequencies
 bool spatial_block_ok(int block, int nsc) { return block == 256 || (block == 512 && nsc <= 2); }
 
-template <int BLOCK, int NSC, bool SEVEN, int KR>
+template <int BLOCK, int NSC, bool SEVEN, int KR, int RHC = 0>
 static hipError_t spatial_launch(const StripArgs &a, hipStream_t s, int *occ)
 {
-    if (occ) return query_occupancy((const void *)spatial_kernel<BLOCK, KR, NSC, SEVEN>, BLOCK, occ);
+    if (occ) return query_occupancy((const void *)spatial_kernel<BLOCK, KR, NSC, SEVEN, RHC>, BLOCK, occ);
+    if (RHC > 0 && a.rh != RHC) return hipErrorInvalidValue;
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
     const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
-    hipLaunchKernelGGL((spatial_kernel<BLOCK, KR, NSC, SEVEN>), grid, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((spatial_kernel<BLOCK, KR, NSC, SEVEN, RHC>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
+}
+
+// The q_2 kernel (one frequency and the constant term: three basis rows per
+// channel, 16 walkers per row) has compile-time-radius kernels for the radii
+// of the plain forward's, whose walkers hand out box sums.
+template <int NSC, bool SEVEN, int KR>
+static hipError_t spatial_radius(const StripArgs &a, hipStream_t s, int *occ)
+{
+    switch (a.rh) {
+    case 3: return spatial_launch<256, NSC, SEVEN, KR, 3>(a, s, occ);
+    case 5: return spatial_launch<256, NSC, SEVEN, KR, 5>(a, s, occ);
+    case 8: return spatial_launch<256, NSC, SEVEN, KR, 8>(a, s, occ);
+    case 10: return spatial_launch<256, NSC, SEVEN, KR, 10>(a, s, occ);
+    case 16: return spatial_launch<256, NSC, SEVEN, KR, 16>(a, s, occ);
+    case 20: return spatial_launch<256, NSC, SEVEN, KR, 20>(a, s, occ);
+    case 25: return spatial_launch<256, NSC, SEVEN, KR, 25>(a, s, occ);
+    case 32: return spatial_launch<256, NSC, SEVEN, KR, 32>(a, s, occ);
+    default: return spatial_launch<256, NSC, SEVEN, KR>(a, s, occ);
+    }
 }
 
 template <int BLOCK, int NSC, bool SEVEN>
 static hipError_t spatial_go(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
+    if constexpr (BLOCK == 256 && NSC == 1 && SEVEN) {
+        if (kc == kr_spatial(NSC)) return spatial_radius<NSC, SEVEN, kr_spatial(NSC)>(a, s, occ);
+        if (kc == kr_spatial_small(NSC)) return spatial_radius<NSC, SEVEN, kr_spatial_small(NSC)>(a, s, occ);
+    }
     if (kc == kr_spatial(NSC)) return spatial_launch<BLOCK, NSC, SEVEN, kr_spatial(NSC)>(a, s, occ);
     if constexpr (BLOCK == 256) {
         if (kc == kr_spatial_small(NSC)) return spatial_launch<BLOCK, NSC, SEVEN, kr_spatial_small(NSC)>(a, s, occ);

@@ -63,6 +63,19 @@ def test_spatial_matches_oracle(shape, r, N, sigma_r, Ns, sigma_s, block):
     assert np.max(err) <= TOL32, (np.max(err), np.unravel_index(np.argmax(err), err.shape))
 
 
+@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+@pytest.mark.parametrize("N,sigma_r", [(30, 30.0),   # 16 orders: four passes of 4
+                                       (0, 1.0)])    # Algorithm 1: one order, the small pass
+def test_q2_compile_time_radius_kernels(r, N, sigma_r):
+    """The q_2 spatial kernel at the radii with compile-time-radius kernels (walkers hand out
+    box sums of all three basis rows), over two strips and several segments."""
+    f = wl.rect_image(60, 300, seed=5 * r + N, n_rect=8)
+    s_s = spatial_sigma_for(r, 2)
+    out = _run(f, r, sigma_r, N, s_s, 2, strip_h=23)
+    ref = oracle.bilateral_sp(f, r, sigma_r, N, s_s, 2)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
 @pytest.mark.parametrize("r,sigma_s,Ns", [(3, 1.5, 2), (10, 4.0, 4), (6, 3.0, 1)])
 def test_algorithm1_linear_filter(r, sigma_s, Ns):
     """Algorithm 1 (the range kernel is 1): the normalised separable linear filter."""
