@@ -193,6 +193,7 @@ static int kernel_occupancy(const Resolved &r, int kind)
     } else if (r.range_kernel == BSK_RANGE_POLY) {
         bsk::PolyArgs pa;
         std::memset(&pa, 0, sizeof(pa));
+        pa.rh = r.rh;
         if (r.prec == BSK_FP64) (void)bsk::launch_poly_f64(pa, r.block, nullptr, &occ);
         else (void)bsk::launch_poly_f32(pa, r.block, r.kc, nullptr, &occ);
     } else if (r.sp.Ns > 0) {

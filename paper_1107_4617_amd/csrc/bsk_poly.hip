@@ -96,7 +96,9 @@ __device__ __forceinline__ AT poly_coef_step(ConstPtr<AT> row, AT u, AT w1, AT w
 
 // MULTI: more than one pass (the workspace carries the partial sums and the
 // recurrence between passes); a single pass compiles without that code.
-template <typename AT, int BLOCK, int KR, int KL, bool MULTI>
+// RHC > 0: the horizontal radius as a compile-time constant; the walkers then
+// hand box sums to the R stage, as in the strip body.
+template <typename AT, int BLOCK, int KR, int KL, bool MULTI, int RHC = 0>
 __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT *lds)
 {
     constexpr int ROWS = 2 * KL;
@@ -113,7 +115,8 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
 
     const IO &a = pa.io;
     const int t = threadIdx.x;
-    const int H = a.H, W = a.W, rh = pa.rh, rv = pa.rv;
+    const int H = a.H, W = a.W, rh = RHC > 0 ? RHC : pa.rh, rv = pa.rv;
+    constexpr bool WBOX = RHC > 0 && sizeof(AT) == 4 && CH == 16 && (2 * RHC + 1) / G + 1 <= 15;
     const int Wt = BLOCK - 2 * rh;
     const int j0 = bx * Wt;
     const int jx = j0 - rh + t;
@@ -222,6 +225,7 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
 #pragma unroll
         for (int q = 0; q < ND; ++q) dd[q] = AT(0);
         AT accQ = AT(0), accP = AT(0);   // Q and 2P of the row in the R stage
+        AT wsQ = AT(0), wsP = AT(0);     // the pass above's Q and 2P, read when the row starts
         int bv = 0;
 
         const int iend = i1 + (NSUB >= 2 ? 1 : 2);
@@ -288,7 +292,10 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                                 w1 = fd;
                             }
                         } else {
-                            // f_{jtop+1} .. f_{jtop+4}, from the pass above
+                            // Q and 2P so far (added when the row ends) and f_{jtop+1} ..
+                            // f_{jtop+4}, from the pass above
+                            wsQ = ws[o];
+                            wsP = ws[plane + o];
                             w1 = ws[2 * plane + o];
                             w2 = ws[3 * plane + o];
                             w3 = ws[4 * plane + o];
@@ -324,9 +331,16 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                     for (int k = 0; k < KL; ++k) {
                         const int m = sR * KL + k;
                         const V2 *prow = VbR + k * RS;
-                        const V2 hi = prow[phi], lo = prow[plo];
-                        const AT Ba = hi.x - lo.x;   // Box[T_{k0+2m}]
-                        const AT Bb = hi.y - lo.y;   // Box[T_{k0+2m+1}]
+                        AT Ba, Bb;   // Box[T_{k0+2m}], Box[T_{k0+2m+1}]
+                        if constexpr (WBOX) {
+                            const V2 bx2 = prow[phi];
+                            Ba = bx2.x;
+                            Bb = bx2.y;
+                        } else {
+                            const V2 hi = prow[phi], lo = prow[plo];
+                            Ba = hi.x - lo.x;
+                            Bb = hi.y - lo.y;
+                        }
                         accQ = fmat(dd[2 * m + 1], Ba, fmat(dd[2 * m + 2], Bb, accQ));
                         accP = fmat(dd[2 * m] + dd[2 * m + 2], Ba, fmat(dd[2 * m + 1] + dd[2 * m + 3], Bb, accP));
                         // x T_0 = T_1 carries d_0 in full: 2P gains another d_0 Box[T_1]
@@ -351,8 +365,23 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                     }
                     const AT off = group_exclusive_scan<CH>(run, wch);
                     if (walker) {
+                        if constexpr (WBOX) {
+                            // box sums: E(p) - E(p - 2 rh - 1), the second a fixed DPP
+                            // shift and element away (strip_body has the derivation)
+                            constexpr int D = 2 * RHC + 1, QS = D / G, DR = D % G;
+                            AT E[G];
 #pragma unroll
-                        for (int u = 0; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
+                            for (int u = 0; u < G; ++u) E[u] = loc[u] + off;
+#pragma unroll
+                            for (int u = 0; u < G; ++u) {
+                                const AT lo = u >= DR ? dpp_row_shr<QS>(E[u >= DR ? u - DR : 0])
+                                                      : dpp_row_shr<QS + 1>(E[u < DR ? u - DR + G : 0]);
+                                VbH[wbase + 2 * u] = E[u] - lo;
+                            }
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < G; ++u) VbH[wbase + 2 * u] = loc[u] + off;
+                        }
                     }
                 }
 
@@ -383,8 +412,8 @@ __device__ __forceinline__ void poly_body(const PolyArgs &pa, int bx, int by, AT
                 if (actR && sR == NSUB - 1 && outlane) {
                     const long o = (long)iR * W + jx;
                     if (!top_pass) {
-                        accQ += ws[o];
-                        accP += ws[plane + o];
+                        accQ += wsQ;
+                        accP += wsP;
                     }
                     if (base) {
                         ((AT *)a.out)[(long)iR * a.pitch_out + jx] = mu + rho * (AT(0.5) * accP / accQ);
@@ -414,33 +443,52 @@ constexpr int poly_minb()
     return BLOCK == 1024 ? 1 : (poly_lds_occupancy(strip_lds_elems<2, KL, BLOCK>() * (int)sizeof(AT)) >= 3 ? 3 : 2);
 }
 
-template <typename AT, int BLOCK, int KR, int KL, bool MULTI>
+template <typename AT, int BLOCK, int KR, int KL, bool MULTI, int RHC = 0>
 __global__ void __launch_bounds__(BLOCK, (poly_minb<AT, BLOCK, KL>())) poly_kernel(const PolyArgs a)
 {
     __shared__ __align__(16) AT lds[strip_lds_elems<2, KL, BLOCK>()];
     int bx, by;
     if (!xcd_tile((a.io.W + BLOCK - 2 * a.rh - 1) / (BLOCK - 2 * a.rh), (a.io.H + a.S - 1) / a.S, &bx, &by)) return;
-    poly_body<AT, BLOCK, KR, KL, MULTI>(a, bx, by, lds);
+    poly_body<AT, BLOCK, KR, KL, MULTI, RHC>(a, bx, by, lds);
 }
 
-template <typename AT, int BLOCK, int KR, int KL>
+template <typename AT, int BLOCK, int KR, int KL, int RHC = 0>
 static hipError_t poly_launch(const PolyArgs &a, hipStream_t s, int *occ)
 {
     if (occ) {
         int n = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, (const void *)poly_kernel<AT, BLOCK, KR, KL, true>, BLOCK, 0);
+            &n, (const void *)poly_kernel<AT, BLOCK, KR, KL, true, RHC>, BLOCK, 0);
         *occ = (e == hipSuccess && n > 0) ? n : 1;
         return e;
     }
+    if (RHC > 0 && a.rh != RHC) return hipErrorInvalidValue;
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1 || a.S < 1 || a.NP < KR || a.NP % KR != 0) return hipErrorInvalidValue;
     const bool multi = a.NP > KR;
     if (multi && !a.ws) return hipErrorInvalidValue;
     const dim3 grid(xcd_grid((a.io.W + Wt - 1) / Wt, (a.io.H + a.S - 1) / a.S));
-    if (multi) hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, true>), grid, dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, false>), grid, dim3(BLOCK), 0, s, a);
+    if (multi) hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, true, RHC>), grid, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((poly_kernel<AT, BLOCK, KR, KL, false, RHC>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
+}
+
+// 256 lanes at the radii of the compile-time-radius strip kernels: walkers
+// that hand out box sums
+template <int KR, int KL>
+static hipError_t poly32_radius(const PolyArgs &a, hipStream_t s, int *occ)
+{
+    switch (a.rh) {
+    case 3: return poly_launch<float, 256, KR, KL, 3>(a, s, occ);
+    case 5: return poly_launch<float, 256, KR, KL, 5>(a, s, occ);
+    case 8: return poly_launch<float, 256, KR, KL, 8>(a, s, occ);
+    case 10: return poly_launch<float, 256, KR, KL, 10>(a, s, occ);
+    case 16: return poly_launch<float, 256, KR, KL, 16>(a, s, occ);
+    case 20: return poly_launch<float, 256, KR, KL, 20>(a, s, occ);
+    case 25: return poly_launch<float, 256, KR, KL, 25>(a, s, occ);
+    case 32: return poly_launch<float, 256, KR, KL, 32>(a, s, occ);
+    default: return poly_launch<float, 256, KR, KL>(a, s, occ);
+    }
 }
 
 template <int BLOCK>
@@ -448,6 +496,10 @@ static hipError_t poly32_block(const PolyArgs &a, int kc, hipStream_t s, int *oc
 {
     constexpr int KR = kr_poly_f32(BLOCK), KL = kl_poly_f32(BLOCK);
     constexpr int KLH = KL < KR / 2 ? KL : KR / 2;
+    if constexpr (BLOCK == 256) {
+        if (kc == KR) return poly32_radius<KR, KL>(a, s, occ);
+        if (kc == KR / 2) return poly32_radius<KR / 2, KLH>(a, s, occ);
+    }
     if (kc == KR) return poly_launch<float, BLOCK, KR, KL>(a, s, occ);
     if (kc == KR / 2) return poly_launch<float, BLOCK, KR / 2, KLH>(a, s, occ);
     return hipErrorInvalidValue;

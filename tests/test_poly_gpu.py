@@ -68,6 +68,26 @@ def test_poly_matches_oracle_fp32(shape, r, sigma_r, N, block):
     assert np.max(err) <= TOL32, (np.max(err), np.unravel_index(np.argmax(err), err.shape))
 
 
+@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+@pytest.mark.parametrize("sigma_r,eps", [(30.0, 0.0),    # 75 coefficients: three passes of 16 pairs
+                                         (60.0, 0.0),    # N = 10: one pass
+                                         (30.0, 1e-7)])  # 26 coefficients: one pass
+def test_poly_compile_time_radius_kernels(r, sigma_r, eps):
+    """The radii with their own polynomial kernels (walkers hand out box sums), over two
+    strips and several segments, with one pass and with several."""
+    f = wl.rect_image(60, 300, seed=7 * r + int(sigma_r), n_rect=8)
+    out = _run(f, r, sigma_r, weight_eps=eps, strip_h=19)
+    Nn = poly_order_for(sigma_r, T)
+    ref, _, Q = oracle.bilateral_poly(f, r, sigma_r, Nn, return_pq=True)
+    bound = 0.0
+    if eps > 0:
+        # the truncated expansion's own bound, as in test_poly_truncated_within_bound
+        _, b = poly_plan_info(sigma_r, T, eps=eps)
+        nwin = (2 * r + 1) ** 2
+        bound = b * nwin * T / (Q - b * nwin)
+    assert np.all(np.abs(out - ref) <= TOL32 + bound)
+
+
 @pytest.mark.parametrize("shape,r,sigma_r,N", [((64, 80), 3, 30.0, None), ((41, 300), 7, 15.0, None),
                                                ((90, 61), 6, 40.0, 21), ((37, 700), 200, 50.0, None),
                                                ((44, 52), 5, 30.0, 0)])
