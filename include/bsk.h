@@ -140,9 +140,10 @@ typedef struct {
  *   T > 0:  range bound, selects N_0
  * Runs on the default stream and synchronises before returning.
  * Performance: with 256-lane strips the radii 3, 5, 8, 10, 16, 20, 25 and 32
- * run kernels compiled for that radius (the plain FP32 forward, and the
- * training forward and adjoint below), 4-9% faster than the run-time-radius
- * kernels every other radius uses; the results agree to FP32 rounding.
+ * run kernels compiled for that radius (the plain FP32 forward, the training
+ * forward and adjoint below, the q_2 spatial kernel and the FP32 polynomial
+ * kernel), up to 9% faster than the run-time-radius kernels every other
+ * radius uses; the results agree to FP32 rounding.
  */
 int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_r, float T,
                         float *out);
