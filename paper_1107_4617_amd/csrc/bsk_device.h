@@ -595,8 +595,16 @@ struct PolBackward {
     template <typename AT>
     __device__ static void recombine(AT v, AT vom, AT C, AT S, const AT *B, const AT *auxc, AT *acc)
     {
+        // the same sum grouped by the centre's C and S:
+        //   C (v Box[aC] + omega v (g_z Box[aS] - Box[a ut S]))
+        // + S (v Box[aS] - omega v (g_z Box[aC] - Box[a ut C])),
+        // six chained multiply-adds when v = 1 (the weight folded into the box sums)
         const AT gz = auxc[0];
-        acc[0] += v * (C * B[0] + S * B[1]) - vom * (S * (gz * B[0] - B[2]) - C * (gz * B[1] - B[3]));
+        const AT t1 = fmat(gz, B[1], -B[3]);
+        const AT t2 = fmat(gz, B[0], -B[2]);
+        const AT u1 = fmat(vom, t1, v * B[0]);
+        const AT u2 = fmat(-vom, t2, v * B[1]);
+        acc[0] = fmat(C, u1, fmat(S, u2, acc[0]));
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
