@@ -170,11 +170,16 @@ static int pick_chunk_poly(int pairs, int N, int full)
 static int kernel_occupancy(const Resolved &r, int kind)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, int, int, int>, int> cache;
-    // the radius picks the compile-time-radius kernels where they exist, whose
-    // register counts (and so residency) differ from the run-time-radius ones
+    static std::map<std::tuple<int, int, int, int, int, int, int, int, int>, int> cache;
+    // the radius picks the compile-time-radius kernels where they exist, and
+    // the padded order count and start mode their one-pass forms, whose
+    // register counts (and so residency) differ from the other kernels'
+    const bool cosine = kind != kPatch2 && r.range_kernel != BSK_RANGE_POLY;
+    const int Kpad = cosine && r.kc > 0 ? (r.plan.K + r.kc - 1) / r.kc * r.kc : 0;
+    const int smode = cosine ? r.plan.start_mode : 0;
     const auto key = std::make_tuple(kind + 3 * r.range_kernel, r.block, r.kc, r.prec, r.kahan,
-                                     r.sp.nsc * 2 + (r.sp.even ? 1 : 0), r.rh, [] {
+                                     r.sp.nsc * 2 + (r.sp.even ? 1 : 0), r.rh,
+                                     Kpad <= r.kc ? smode : 2 + smode, [] {
         int d = 0;
         (void)hipGetDevice(&d);
         return d;
@@ -187,6 +192,8 @@ static int kernel_occupancy(const Resolved &r, int kind)
     bsk::StripArgs a;
     std::memset(&a, 0, sizeof(a));
     a.rh = r.rh;
+    a.K = Kpad;
+    a.start_mode = smode;
     int occ = 1;
     if (kind == kPatch2) {
         (void)bsk::launch_patch2_f32(a, r.block, r.kc, 0, nullptr, &occ);

@@ -289,7 +289,7 @@ __device__ __forceinline__ T ld(const void *p, long idx) { return ((const T *)p)
 // 1: odd N), so the start's selects and the general-angle path compile away.
 template <typename FT, int SM = -1>
 struct PolForward {
-    static constexpr int NCH = 4, NACC = 2, NAUX = 1, NRAW = 1, NPAIR = 2;
+    static constexpr int NCH = 4, NACC = 2, NAUX = 1, NRAW = 1, NPAIR = 2, NCTR = 0;
     static constexpr int START = SM;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
@@ -339,7 +339,7 @@ struct PolForward {
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
-                                    double *red)
+                                    const AT *ctr, double *red)
     {
         ((FT *)a.out)[(long)i * a.pitch_out + j] = (FT)(ref + acc[1] / acc[0]);
     }
@@ -357,7 +357,7 @@ struct PolForward {
 // orders per pass range.
 template <int G>
 struct PolPatch2G {
-    static constexpr int NCH = 4, NACC = 2, NAUX = 2, NRAW = 2, NPAIR = 2;
+    static constexpr int NCH = 4, NACC = 2, NAUX = 2, NRAW = 2, NPAIR = 2, NCTR = 0;
     static constexpr int START = -1;
     static constexpr int GROUP = G;
     template <typename AT>
@@ -394,7 +394,7 @@ struct PolPatch2G {
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
-                                    double *red)
+                                    const AT *ctr, double *red)
     {
         ((float *)a.out)[(long)i * a.pitch_out + j] = (float)(ref + acc[1] / acc[0]);
     }
@@ -463,7 +463,7 @@ __device__ __forceinline__ void chain_restart(CH &ch, int m)
 // phi'(t) = -sum_m v_m omega_m sin(omega_m t).  Outputs u = ref + P/Q and the
 // planes Q, E1 = A1 - (u-ref) A0, E2 = A2 - (g_z + u - ref) A1 + g_z (u-ref) A0.
 struct PolTrain {
-    static constexpr int NCH = 6, NACC = 5, NAUX = 1, NRAW = 1, NPAIR = 3;
+    static constexpr int NCH = 6, NACC = 5, NAUX = 1, NRAW = 1, NPAIR = 3, NCTR = 0;
     static constexpr int START = -1;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
@@ -512,7 +512,7 @@ struct PolTrain {
     }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
-                                    double *red)
+                                    const AT *ctr, double *red)
     {
         const AT Q = acc[0];
         const AT ut = acc[1] / Q;
@@ -548,10 +548,12 @@ struct FoldsWeight<PolTrain> {
 //   T1(z) = sum_m v_m { C(z) Box[aC] + S(z) Box[aS]
 //           - omega_m [ S(z) (g_z Box[aC] - Box[a ut C]) - C(z) (g_z Box[aS] - Box[a ut S]) ] }
 // and dL/df(z) = T1(z) - alpha(z) E1(z); per-workgroup partial sums of
-// alpha(x) E2(x) feed dL/dsigma_r.
+// alpha(x) E2(x) feed dL/dsigma_r.  SM >= 0 fixes a one-pass launch's chain
+// start mode, as for the forward.
+template <int SM = -1>
 struct PolBackward {
-    static constexpr int NCH = 4, NACC = 1, NAUX = 3, NRAW = 4, NPAIR = 2;
-    static constexpr int START = -1;
+    static constexpr int NCH = 4, NACC = 1, NAUX = 3, NRAW = 4, NPAIR = 2, NCTR = 2;
+    static constexpr int START = SM;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
     {
@@ -606,18 +608,32 @@ struct PolBackward {
         const AT u2 = fmat(-vom, t2, v * B[1]);
         acc[0] = fmat(C, u1, fmat(S, u2, acc[0]));
     }
+    // the zero frequency: S = 0 and omega = 0, so only C(z) v Box[aC] remains
+    template <typename AT>
+    __device__ static void recombine_s0(AT v, AT C, const AT *B, AT *acc)
+    {
+        acc[0] = fmat(v * C, B[0], acc[0]);
+    }
+    // E1 and E2 of the output pixel, loaded when its row's R stage starts
+    template <typename AT>
+    __device__ static void fetch_centre(const IO &a, int i, int j, AT *ctr)
+    {
+        const long o = (long)i * a.W + j;
+        ctr[0] = (AT)a.aux3[o];
+        ctr[1] = (AT)a.aux4[o];
+    }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
-                                    double *red)
+                                    const AT *ctr, double *red)
     {
         const long o = (long)i * a.W + j;
         const AT alpha = auxc[1];
-        if (a.out) ((float *)a.out)[o] = (float)(acc[0] - alpha * (AT)a.aux3[o]);
-        *red += (double)alpha * (double)a.aux4[o];
+        if (a.out) ((float *)a.out)[o] = (float)(acc[0] - alpha * ctr[0]);
+        *red += (double)alpha * (double)ctr[1];
     }
 };
-template <>
-struct FoldsWeight<PolBackward> {
+template <int SM>
+struct FoldsWeight<PolBackward<SM>> {
     static constexpr bool value = true;
 };
 
@@ -1052,6 +1068,15 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
         AT wsv[NACC];
 #pragma unroll
         for (int q = 0; q < NACC; ++q) wsv[q] = AT(0);
+        // per-pixel inputs that only the last pass's finalisation reads, loaded
+        // one row ahead for the same reason
+        constexpr int NCTR = POL::NCTR;
+        AT ctr[NCTR > 0 ? NCTR : 1];
+#pragma unroll
+        for (int q = 0; q < (NCTR > 0 ? NCTR : 1); ++q) ctr[q] = AT(0);
+        if constexpr (NCTR > 0) {
+            if (last && outlane) POL::template fetch_centre<AT>(a, i0, jx, ctr);
+        }
         // spatial kernel: kappa times the phases of the incoming and outgoing
         // rows, and u_j (cos, sin)(nu_j i) of the output row
         AT kic[NPAIR][NSCR], kis[NPAIR][NSCR], koc[NPAIR][NSCR], kos[NPAIR][NSCR];
@@ -1404,7 +1429,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                                 acc[1] = auxc[0];
                             }
                         }
-                        POL::template finalize<AT>(a, iR, jx, ref, auxc, acc, &red);
+                        POL::template finalize<AT>(a, iR, jx, ref, auxc, acc, ctr, &red);
+                        if constexpr (NCTR > 0) POL::template fetch_centre<AT>(a, rowc(iR + 1), jx, ctr);
                     } else {
 #pragma unroll
                         for (int q = 0; q < NACC; ++q) ((AT *)gm.ws)[q * plane + o] = acc[q];
@@ -1417,7 +1443,9 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     }
 
     if (red_out) {
-        // deterministic block reduction (fixed order) of the per-lane sums
+        // deterministic block reduction (fixed order) of the per-lane sums; the
+        // barrier first, as red_lds may alias the row buffers
+        __syncthreads();
         red_lds[t] = red;
         __syncthreads();
         if (t == 0) {

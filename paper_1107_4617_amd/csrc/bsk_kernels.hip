@@ -81,7 +81,7 @@ int chunk_train_f32(int block) { return kr_train(block); }
 int chunk_backward_f32(int block) { return kr_bwd(block); }
 int acc_count_forward() { return PolForward<float>::NACC; }
 int acc_count_train() { return PolTrain::NACC; }
-int acc_count_backward() { return PolBackward::NACC; }
+int acc_count_backward() { return PolBackward<>::NACC; }
 
 template <int BLOCK, int QUANT, bool KAHAN>
 static hipError_t fwd32_block(const StripArgs &a, int kc, hipStream_t s, int *occ)

@@ -21,7 +21,7 @@
 // recurrence in k run downwards from d_2N (bsk_plan.cpp), six multiply-adds
 // per coefficient.  The channels come from the three-term recurrence
 // T_{k+1} = 2 x T_k - T_{k-1}, one multiply-add per value.
-#include "bsk_device.h"
+#include "bsk_strip.h"
 
 namespace bsk {
 
@@ -455,13 +455,7 @@ __global__ void __launch_bounds__(BLOCK, (poly_minb<AT, BLOCK, KL>())) poly_kern
 template <typename AT, int BLOCK, int KR, int KL, int RHC = 0>
 static hipError_t poly_launch(const PolyArgs &a, hipStream_t s, int *occ)
 {
-    if (occ) {
-        int n = 0;
-        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, (const void *)poly_kernel<AT, BLOCK, KR, KL, true, RHC>, BLOCK, 0);
-        *occ = (e == hipSuccess && n > 0) ? n : 1;
-        return e;
-    }
+    if (occ) return query_occupancy((const void *)poly_kernel<AT, BLOCK, KR, KL, true, RHC>, BLOCK, occ);
     if (RHC > 0 && a.rh != RHC) return hipErrorInvalidValue;
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1 || a.S < 1 || a.NP < KR || a.NP % KR != 0) return hipErrorInvalidValue;

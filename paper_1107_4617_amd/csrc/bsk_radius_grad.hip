@@ -16,14 +16,23 @@ hipError_t train_radius(const StripArgs &a, hipStream_t s, int *occ)
     return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3, R>(a, s, occ);
 }
 
+// one pass with the start mode as a constant, else passes with the run-time mode
+template <int R, int KR, int MINB>
+hipError_t backward_radius_pass(const StripArgs &a, hipStream_t s, int *occ)
+{
+    if (a.K <= KR && a.start_mode == 0) return bwd<256, KR, 4, MINB, R, 0>(a, s, occ);
+    if (a.K <= KR && a.start_mode == 1) return bwd<256, KR, 4, MINB, R, 1>(a, s, occ);
+    return bwd<256, KR, 4, MINB, R>(a, s, occ);
+}
+
 // the pass shapes of bwd_block<256>: the 24- and 16-order passes at two
 // workgroups per CU, the 8-order half pass at three
 template <int R>
 hipError_t backward_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
     switch (kc) {
-    case 24: return bwd<256, 24, 4, 2, R>(a, s, occ);
-    case 16: return bwd<256, 16, 4, 0, R>(a, s, occ);
+    case 24: return backward_radius_pass<R, 24, 2>(a, s, occ);
+    case 16: return backward_radius_pass<R, 16, 0>(a, s, occ);
     case 8: return bwd<256, 8, 4, 3, R>(a, s, occ);
     default: return hipErrorInvalidValue;
     }

@@ -7,8 +7,9 @@
 
 namespace bsk {
 
-// Workgroups per compute unit that the LDS row buffers allow (160 KiB per CU).
-constexpr int lds_occupancy(int bytes) { return bytes <= 160 * 1024 / 3 ? 3 : bytes <= 80 * 1024 ? 2 : 1; }
+// Workgroups per compute unit that the LDS row buffers allow (160 KiB per CU,
+// counted in 2 KiB units as in query_occupancy).
+constexpr int lds_occupancy(int bytes) { return bytes <= 52 * 1024 ? 3 : bytes <= 80 * 1024 ? 2 : 1; }
 
 // Pass shapes per lane count: KR orders in registers per pass and KL orders per
 // pipeline interval (NCH * KL LDS rows per buffer).  The three row buffers stay
@@ -125,31 +126,48 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, K
     }
 }
 
-// The adjoint over a stack of images; RHC as for strip_kernel.
-template <int BLOCK, int KR, int KL, int MINB = 0, int RHC = 0>
-__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward::NCH, KL, BLOCK, float>()))
+// The adjoint over a stack of images; RHC as for strip_kernel, SM >= 0 a
+// one-pass launch (K <= KR) with that chain start mode.
+template <int BLOCK, int KR, int KL, int MINB = 0, int RHC = 0, int SM = -1>
+__global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<PolBackward<>::NCH, KL, BLOCK, float>()))
     backward_kernel(const StripArgs a)
 {
-    __shared__ __align__(16) float lds[lds_elems<PolBackward::NCH, KL, BLOCK, float>()];
-    __shared__ double red_lds[BLOCK];
+    // the block reduction of the sigma_r partial sums reuses the row buffers
+    // once the rows are done, so it adds no LDS (three workgroups per compute
+    // unit fit where the row buffers alone allow it)
+    constexpr int NL = lds_elems<PolBackward<>::NCH, KL, BLOCK, float>();
+    static_assert(NL * sizeof(float) >= BLOCK * sizeof(double), "the reduction fits in the row buffers");
+    __shared__ __align__(16) float lds[NL];
+    double *const red_lds = reinterpret_cast<double *>(lds);
     int bx, by, b;
     if (!stack_tile(a, &bx, &by, &b)) return;
     const IO io = stack_io(a, b);
     const Geom gm = stack_geom(a, b);
     // one partial sum per tile of the whole stack, image-major like the tiles
     const long segs = (a.io.H + a.S - 1) / a.S;
-    strip_body<float, BLOCK, KR, KL, PolBackward, 0, false, 0, true, RHC>(
+    strip_body<float, BLOCK, KR, KL, PolBackward<SM>, 0, false, 0, true, RHC>(
         io, gm, bx, by, lds, red_lds, a.red + (((long)b * segs + by) * a.strips + bx));
 }
 
 // ---------------------------------------------------------------- launches --
 // Every launch helper either launches (occ == nullptr) or reports, in *occ,
 // how many workgroups of that exact kernel one compute unit holds.
+// The runtime's answer is capped by the kernel's LDS counted in 2 KiB units
+// out of 160 KiB: a 53 KiB workgroup (54,272 bytes) that the runtime placed
+// three to a compute unit ran only two at a time, which sized a launch for one
+// and a half rounds of workgroups; 51 KiB ones do run three at a time.
 inline hipError_t query_occupancy(const void *kernel, int block, int *occ)
 {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0);
     *occ = (e == hipSuccess && n > 0) ? n : 1;
+    hipFuncAttributes fa;
+    if (e == hipSuccess && hipFuncGetAttributes(&fa, kernel) == hipSuccess && fa.sharedSizeBytes > 0) {
+        constexpr long kUnit = 2048, kLds = 160 * 1024;
+        const long units = ((long)fa.sharedSizeBytes + kUnit - 1) / kUnit;
+        const int by_lds = (int)(kLds / (units * kUnit));
+        if (by_lds >= 1 && *occ > by_lds) *occ = by_lds;
+    }
     return e;
 }
 
@@ -167,16 +185,17 @@ static hipError_t launch(const StripArgs &a, hipStream_t s, int *occ)
     return hipGetLastError();
 }
 
-template <int BLOCK, int KR, int KL, int MINB, int RHC = 0>
+template <int BLOCK, int KR, int KL, int MINB, int RHC = 0, int SM = -1>
 static hipError_t bwd(const StripArgs &a, hipStream_t s, int *occ)
 {
-    if (occ) return query_occupancy((const void *)backward_kernel<BLOCK, KR, KL, MINB, RHC>, BLOCK, occ);
+    if (occ) return query_occupancy((const void *)backward_kernel<BLOCK, KR, KL, MINB, RHC, SM>, BLOCK, occ);
     if (RHC > 0 && a.rh != RHC) return hipErrorInvalidValue;
+    if (SM >= 0 && (a.K > KR || a.start_mode != SM)) return hipErrorInvalidValue;
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
     const dim3 grid(xcd_grid(a.strips, strip_tiles(a) / a.strips));
-    hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB, RHC>), grid, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((backward_kernel<BLOCK, KR, KL, MINB, RHC, SM>), grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
