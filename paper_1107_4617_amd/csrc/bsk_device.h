@@ -462,9 +462,11 @@ __device__ __forceinline__ void chain_restart(CH &ch, int m)
 //   = -sum_m v_m omega_m [C_m(z) Box[g^p S_m] - S_m(z) Box[g^p C_m]],
 // phi'(t) = -sum_m v_m omega_m sin(omega_m t).  Outputs u = ref + P/Q and the
 // planes Q, E1 = A1 - (u-ref) A0, E2 = A2 - (g_z + u - ref) A1 + g_z (u-ref) A0.
+// SM >= 0 fixes a one-pass launch's chain start mode, as for the forward.
+template <int SM = -1>
 struct PolTrain {
     static constexpr int NCH = 6, NACC = 5, NAUX = 1, NRAW = 1, NPAIR = 3, NCTR = 0;
-    static constexpr int START = -1;
+    static constexpr int START = SM;
     template <typename AT>
     __device__ static void kappa(const AT *aux, AT *k)
     {
@@ -510,6 +512,14 @@ struct PolTrain {
         acc[3] = fmat(ws, B[2], fmat(-wc, B[3], acc[3]));
         acc[4] = fmat(ws, B[4], fmat(-wc, B[5], acc[4]));
     }
+    // the zero frequency: S = 0 and omega = 0, so the A_p terms vanish
+    template <typename AT>
+    __device__ static void recombine_s0(AT v, AT C, const AT *B, AT *acc)
+    {
+        const AT vc = v * C;
+        acc[0] = fmat(vc, B[0], acc[0]);
+        acc[1] = fmat(vc, B[2], acc[1]);
+    }
     template <typename AT>
     __device__ static void finalize(const IO &a, int i, int j, AT ref, const AT *auxc, const AT *acc,
                                     const AT *ctr, double *red)
@@ -538,8 +548,8 @@ template <typename FT, int SM>
 struct FoldsWeight<PolForward<FT, SM>> {
     static constexpr bool value = true;
 };
-template <>
-struct FoldsWeight<PolTrain> {
+template <int SM>
+struct FoldsWeight<PolTrain<SM>> {
     static constexpr bool value = true;
 };
 

@@ -80,7 +80,7 @@ int chunk_forward_f64(int block) { return kr_f64(block); }
 int chunk_train_f32(int block) { return kr_train(block); }
 int chunk_backward_f32(int block) { return kr_bwd(block); }
 int acc_count_forward() { return PolForward<float>::NACC; }
-int acc_count_train() { return PolTrain::NACC; }
+int acc_count_train() { return PolTrain<>::NACC; }
 int acc_count_backward() { return PolBackward<>::NACC; }
 
 template <int BLOCK, int QUANT, bool KAHAN>
@@ -225,9 +225,9 @@ hipError_t launch_train_f32(const StripArgs &a, int block, int kc, hipStream_t s
     // orders at 16 x 1024^2)
     if (kc != kr_train(block)) return hipErrorInvalidValue;
     switch (block) {
-    case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain, 0, false, 3>(a, s, occ);
-    case 512: return launch<float, 512, kr_train(512), kl_train(512), PolTrain, 0, false>(a, s, occ);
-    case 1024: return launch<float, 1024, kr_train(1024), kl_train(1024), PolTrain, 0, false>(a, s, occ);
+    case 256: return launch<float, 256, kr_train(256), kl_train(256), PolTrain<>, 0, false, 3>(a, s, occ);
+    case 512: return launch<float, 512, kr_train(512), kl_train(512), PolTrain<>, 0, false>(a, s, occ);
+    case 1024: return launch<float, 1024, kr_train(1024), kl_train(1024), PolTrain<>, 0, false>(a, s, occ);
     default: return hipErrorInvalidValue;
     }
 }

@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(BLOCK, MINB ? MINB : (default_minb<POL::NCH, K
 {
     __shared__ __align__(16) AT lds[lds_elems<POL::NCH, KL, BLOCK, AT>()];
     int bx, by;
-    if constexpr (std::is_same<POL, PolTrain>::value) {
+    if constexpr (std::is_same<POL, PolTrain<POL::START>>::value) {
         // the training forward also runs over image stacks
         int b;
         if (!stack_tile(a, &bx, &by, &b)) return;
@@ -177,6 +177,7 @@ static hipError_t launch(const StripArgs &a, hipStream_t s, int *occ)
     if (occ)
         return query_occupancy((const void *)strip_kernel<AT, BLOCK, KR, KL, POL, QUANT, KAHAN, MINB, RHC>, BLOCK, occ);
     if (RHC > 0 && a.rh != RHC) return hipErrorInvalidValue;
+    if (POL::START >= 0 && (a.K > KR || a.start_mode != POL::START)) return hipErrorInvalidValue;
     const int Wt = BLOCK - 2 * a.rh;
     if (Wt < 1) return hipErrorInvalidValue;
     if (a.strips != (a.io.W + Wt - 1) / Wt) return hipErrorInvalidValue;
