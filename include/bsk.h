@@ -139,11 +139,13 @@ typedef struct {
  *   sigma_r > 0: range scale (the Gaussian limit's standard deviation)
  *   T > 0:  range bound, selects N_0
  * Runs on the default stream and synchronises before returning.
- * Performance: with 256-lane strips the radii 3, 5, 8, 10, 16, 20, 25 and 32
- * run kernels compiled for that radius (the plain FP32 forward, the training
- * forward and adjoint below, the q_2 spatial kernel and the FP32 polynomial
- * kernel), up to 9% faster than the run-time-radius kernels every other
- * radius uses; the results agree to FP32 rounding.
+ * Performance: with 256-lane strips (the default for r <= 64) every radius
+ * from 1 to 32 runs kernels compiled for that radius in the plain FP32
+ * forward and in the training forward and adjoint below, and the radii 3, 5,
+ * 8, 10, 16, 20, 25 and 32 also in the q_2 spatial kernel and the FP32
+ * polynomial kernel.  They are 3-9% faster than the run-time-radius kernels
+ * the other radii use (the adjoint about 25%); the results agree to FP32
+ * rounding.
  */
 int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_r, float T,
                         float *out);

@@ -9,7 +9,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsk.so")
-SOURCES = ["bsk_kernels.hip", "bsk_radius.hip", "bsk_radius_grad.hip", "bsk_batched.hip", "bsk_poly.hip", "bsk_noalloc.hip", "bsk_plan.cpp",
+# the largest sources first, so the parallel build finishes sooner
+SOURCES = ["bsk_radius_1_8.hip", "bsk_radius_9_16.hip", "bsk_radius_17_24.hip", "bsk_radius_25_32.hip",
+           "bsk_kernels.hip", "bsk_poly.hip", "bsk_radius.hip", "bsk_batched.hip", "bsk_noalloc.hip", "bsk_plan.cpp",
            "bsk_api.cpp", "bsk_batched.cpp"]
 
 # Packed FP32 instructions are turned off in the device code; hipcc's host

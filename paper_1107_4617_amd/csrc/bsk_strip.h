@@ -1,6 +1,6 @@
 // The strip kernels (single image, image stacks, adjoint) and their launch
-// helpers, shared by the launch files (bsk_kernels.hip, bsk_radius.hip,
-// bsk_radius_grad.hip).  The kernel body and its design
+// helpers, shared by the launch files (bsk_kernels.hip, bsk_poly.hip and the
+// compile-time-radius files, bsk_radius.h).  The kernel body and its design
 // are in bsk_device.h.
 #pragma once
 #include "bsk_device.h"

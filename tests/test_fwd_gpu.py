@@ -110,7 +110,12 @@ def test_shapes_and_edge_cases(shape, r, N, sigma, block, strip_h):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
-@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+# Radii on both sides of the walker-chunk multiples (the box width 2r + 1 against 17,
+# 34 and 51 positions: r = 8, 16/17, 24/25) and in each of the four compiled parts.
+CT_RADII = [1, 2, 3, 5, 7, 8, 10, 13, 16, 17, 20, 24, 25, 31, 32]
+
+
+@pytest.mark.parametrize("r", CT_RADII)
 @pytest.mark.parametrize("N,sigma", [(30, 30.0),    # 16 orders, even N: the full pass
                                      (31, 30.0),    # 16 orders, odd N
                                      (7, 70.0)])    # 4 orders, odd N: the half pass
@@ -123,7 +128,17 @@ def test_compile_time_radius_kernels(r, N, sigma):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
-@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
+@pytest.mark.parametrize("r", range(1, 33))
+def test_every_compile_time_radius(r):
+    """Every radius from 1 to 32 has its own kernel: the headline's order count on a
+    small image with two strips and ragged segments."""
+    f = wl.rect_image(70, 330, seed=100 + r, n_rect=8)
+    ref = oracle.bilateral(f, r, 30.0, 30)
+    out = _gpu_filter(f, r, 30.0, N=30, strip_h=23)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
+@pytest.mark.parametrize("r", CT_RADII)
 @pytest.mark.parametrize("N,sigma", [(20, 36.0),    # 11 orders: one 12-order pass
                                      (43, 25.0),    # 22 orders: two 12-order passes
                                      (117, 15.0)])  # 59 orders: four 16-order passes

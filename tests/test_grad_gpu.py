@@ -118,10 +118,17 @@ def test_rect4096_adjoint_sampled():
     assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("r", [3, 5, 8, 10, 16, 20, 25, 32])
-@pytest.mark.parametrize("N,sigma", [(30, 30.0),    # 16 orders: two training passes of 8, one adjoint pass of 16
-                                     (43, 25.0),    # 22 orders: three training passes, one adjoint pass of 24
-                                     (7, 70.0)])    # 4 orders: one training pass, the adjoint's half pass
+# Radii on both sides of the walker-chunk multiples and in each of the four compiled parts.
+CT_RADII = [1, 2, 3, 5, 7, 8, 10, 13, 16, 17, 20, 24, 25, 31, 32]
+
+
+@pytest.mark.parametrize("r", CT_RADII)
+@pytest.mark.parametrize("N,sigma", [(30, 30.0),    # 16 orders, even N: two training passes of 8, one adjoint pass of 16
+                                     (31, 30.0),    # 16 orders, odd N
+                                     (43, 25.0),    # 22 orders, odd N: three training passes, one adjoint pass of 24
+                                     (42, 25.0),    # 22 orders, even N
+                                     (7, 70.0),     # 4 orders, odd N: one training pass, the adjoint's half pass
+                                     (8, 70.0)])    # 5 orders, even N
 def test_compile_time_radius_gradients(r, N, sigma):
     """The radii with their own training-forward and adjoint kernels (the walkers hand out box
     sums), across two strips and several segments: output, saved normaliser and both gradients
