@@ -1276,7 +1276,12 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         if constexpr (FOLDV) {
                             // the prefixes of order m scaled by its weight v_m
                             const AT vw = vH[floormod(h - 1, NSUB)];
-                            const AT offv = off * vw;
+                            // a multiply-add with a zero addend is the rounded product, and
+                            // keeps the compiler from fusing it into the box subtraction
+                            // below (E(p) - E(p - D) at u = 0): the box sums are then the
+                            // same as the differences of the stored prefixes that the
+                            // run-time-radius kernels take, bit for bit
+                            const AT offv = fmat(off, vw, AT(0));
                             if constexpr (WBOX) {
                                 // position p = G w + u: E(p - D), D = 2 rh + 1, is element
                                 // u - D mod G of walker w - QS (u >= DR) or of walker

@@ -239,6 +239,16 @@ static hipError_t bwd_block(const StripArgs &a, int kc, hipStream_t s, int *occ)
     constexpr int KR = kr_bwd(BLOCK), KL = kl_bwd(BLOCK);
     // a radius with its own kernels
     if (backward_radius_kernel(BLOCK, a.rh, kc)) return launch_backward_f32_radius(a, kc, s, occ);
+    if constexpr (BLOCK == 256) {
+        // one pass of 16 or 24 orders with the start mode as a constant (the
+        // 16-order one then runs three workgroups per CU)
+        if (a.K <= kc && (a.start_mode == 0 || a.start_mode == 1)) {
+            if (kc == KR)
+                return a.start_mode == 0 ? bwd<256, KR, KL, 0, 0, 0>(a, s, occ) : bwd<256, KR, KL, 0, 0, 1>(a, s, occ);
+            if (kc == big_chunk_backward_f32(256))
+                return a.start_mode == 0 ? bwd<256, 24, 4, 2, 0, 0>(a, s, occ) : bwd<256, 24, 4, 2, 0, 1>(a, s, occ);
+        }
+    }
     if (kc == KR) return bwd<BLOCK, KR, KL, 0>(a, s, occ);
     if constexpr (BLOCK == 256) {
         if (kc == mid_chunk_backward_f32(256)) return bwd<256, 12, 4, 3>(a, s, occ);

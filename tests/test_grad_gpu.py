@@ -145,6 +145,34 @@ def test_compile_time_radius_gradients(r, N, sigma):
     assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
 
 
+@pytest.mark.parametrize("r", [0, 33, 47])
+@pytest.mark.parametrize("N,sigma", [(30, 30.0), (31, 30.0), (43, 25.0), (42, 25.0), (7, 70.0)])
+def test_run_time_radius_gradients(r, N, sigma):
+    """256-lane strips at radii without compile-time-radius kernels (0 and above 32): the
+    one-pass 16- and 24-order adjoints with the start mode as a constant, both modes, and
+    the half pass, against the oracle."""
+    f = wl.rect_image(36, 300, seed=7 * r + N, n_rect=8)
+    g = np.random.default_rng(r + 2 * N).normal(size=f.shape)
+    gf_ref, gs_ref, u_ref = oracle.bilateral_grad(f.astype(np.float64), g, r, sigma, N)
+    x = _cuda(f)
+    out, saved = bilateral_train(x, r, sigma, T, N)
+    assert np.max(np.abs(out.cpu().numpy() - u_ref)) <= 1e-4 * T
+    gi, gs = bilateral_backward(x, _cuda(g), r, sigma, T, N, out=out, saved=saved)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(gi.cpu().numpy() - gf_ref)) <= 1e-3 * max(np.max(np.abs(gf_ref)), 1e-12)
+    if r == 0:
+        # the exact sigma_r gradient is 0, and the kernel's is the FP32 rounding of
+        # C (g S) - S (g C) summed over the image
+        return
+    # The sigma_r gradient sums g(x) du(x)/dsigma_r, terms of both signs: bounded by 1e-3 of
+    # it plus 1e-5 of the sum of the terms' sizes (from central differences of the oracle),
+    # which covers sums that nearly cancel.
+    h = 1e-3 * sigma
+    du = (oracle.bilateral(f, r, sigma + h, N) - oracle.bilateral(f, r, sigma - h, N)) / (2 * h)
+    size = float(np.sum(np.abs(g) * np.abs(du)))
+    assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref) + 1e-5 * size
+
+
 @pytest.mark.parametrize("shape,r", [((1, 1), 20), ((5, 40), 32), ((50, 3), 10)])
 def test_compile_time_radius_gradients_small_images(shape, r):
     """Compile-time-radius training forward and adjoint on images smaller than the window."""
