@@ -1279,8 +1279,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                             // a multiply-add with a zero addend is the rounded product, and
                             // keeps the compiler from fusing it into the box subtraction
                             // below (E(p) - E(p - D) at u = 0): the box sums are then the
-                            // same as the differences of the stored prefixes that the
-                            // run-time-radius kernels take, bit for bit
+                            // same subtractions of the same prefix values that the
+                            // run-time-radius kernels make in their R stage
                             const AT offv = fmat(off, vw, AT(0));
                             if constexpr (WBOX) {
                                 // position p = G w + u: E(p - D), D = 2 rh + 1, is element
