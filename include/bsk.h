@@ -95,7 +95,8 @@ typedef struct {
     int block;            /* lanes per workgroup (256, 512, 1024); 0 = auto */
     int strip_h;          /* output rows per workgroup; 0 = auto */
     int order_chunk;      /* orders per pass, one of the pass sizes of the kernel that runs:
-                             FP32 forward 256: 16|12|8 (12: plain FP32 stack only), 512: 8|4,
+                             FP32 forward 256: 24|20|16|12|8 (12: plain FP32 stack only; 24
+                             and 20: plain FP32 stack at radii 1 to 32), 512: 8|4,
                              1024: 4|2 (lanes: full|half); adjoint 256: 24|16|12|8, 512: 8|4,
                              1024: 2|1; batched 256: 16|12|8, 512: 8|4, 1024: 4|2; spatial kernel 4|2
                              (one frequency) or 2|1; polynomial range kernel (channel pairs)
@@ -368,7 +369,7 @@ int bsk_poly_plan_info(int N, float sigma_r, float T, double eps, int *coefs, do
 
 /*
  * Launch-shape autotuner.  Times the candidate shapes (lanes per workgroup in
- * {256, 512, 1024} that fit the radius, the block's two pass sizes, output
+ * {256, 512, 1024} that fit the radius, the block's pass sizes, output
  * rows per workgroup in {16 .. 256}) of the single-image forward for this exact request on the
  * current device, using the caller's img and out buffers (out is overwritten
  * several times; the stream is synchronised), and caches the fastest.  Later

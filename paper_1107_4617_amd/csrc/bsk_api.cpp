@@ -120,15 +120,24 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // the one with the lower estimated cost, counting the padded orders each pass
 // runs and about 2.5 + kc / 10 orders' worth of per-pass work (window
 // initialisation, recurrence starts, workspace traffic).
+// padded orders plus a per-pass cost (window initialisation, three recurrence
+// starts per row, workspace traffic) of about 5 + kc / 10 orders
+static double chunk_cost(int K, int kc) { return ((K + kc - 1) / kc) * (kc + 5.0 + 0.1 * kc); }
+
 int pick_chunk(int K, int full, int small, int mid)
 {
     if (small == 0) small = full / 2;
-    // padded orders plus a per-pass cost (window initialisation, three recurrence
-    // starts per row, workspace traffic) of about 5 + kc / 10 orders
-    auto cost = [K](int kc) { return ((K + kc - 1) / kc) * (kc + 5.0 + 0.1 * kc); };
     int best = full;
-    if (small >= 1 && small != full && cost(small) < cost(best)) best = small;
-    if (mid > 0 && cost(mid) < cost(best)) best = mid;
+    if (small >= 1 && small != full && chunk_cost(K, small) < chunk_cost(K, best)) best = small;
+    if (mid > 0 && chunk_cost(K, mid) < chunk_cost(K, best)) best = mid;
+    return best;
+}
+
+int pick_chunk_of(int K, const int *sizes, int n)
+{
+    int best = sizes[0];
+    for (int i = 1; i < n; ++i)
+        if (chunk_cost(K, sizes[i]) < chunk_cost(K, best)) best = sizes[i];
     return best;
 }
 
@@ -405,10 +414,12 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
         const int one = bsk::onepass_chunk_forward_f64(block);
         kc = (one && r->plan.K <= one && r->plan.start_mode <= 1) ? one : bsk::chunk_forward_f64(block);
     } else {
-        // the 12-order pass exists for the plain FP32 stack
-        const int mid = (r->prec == BSK_FP32 && !r->kahan) ? bsk::mid_chunk_forward_f32(block) : 0;
-        if (kc == 0) kc = pick_chunk(r->plan.K, bsk::chunk_forward_f32(block), 0, mid);
-        if (!bsk::valid_chunk_forward_f32(block, kc) && !(mid && kc == mid))
+        // the plain FP32 stack at 256 lanes has 8, 12 and 16 orders per pass (and
+        // 20 and 24 at the compile-time radii), the others the full and the half pass
+        int sizes[bsk::kMaxForwardChunks];
+        const int n = bsk::forward_chunks_f32(block, r->prec, r->kahan, r->rh, sizes);
+        if (kc == 0) kc = pick_chunk_of(r->plan.K, sizes, n);
+        if (!bsk::forward_chunk_ok_f32(block, r->prec, r->kahan, r->rh, kc))
             return fail(BSK_EINVAL, "order_chunk %d is not a pass size of a %d-lane block", kc, block);
     }
     r->kc = kc;

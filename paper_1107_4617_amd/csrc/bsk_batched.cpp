@@ -697,20 +697,19 @@ int bsk_autotune(const void *img, int H, int W, int radius, float sigma_r, float
     for (int b : blocks) {
         if (b - 2 * base.rh < b / 4 && !(b == 1024 && base.rh <= 511)) continue;
         if (b - 2 * base.rh < 1) continue;
-        const int full = bsk::chunk_forward_f32(b);
-        // the 12-order pass exists for the plain FP32 stack
-        const int mid = (base.prec == BSK_FP32 && !base.kahan) ? bsk::mid_chunk_forward_f32(b) : 0;
-        const int kcs[3] = {full, mid, full / 2};
-        for (int kc : kcs) {
-            if (kc <= 0) continue;
-            // the FP64 forward has a single pass size
-            if (base.prec == BSK_FP64 && kc != full) continue;
+        // every pass size of the stack at this lane count (the FP64 forward has
+        // a single one, chosen by the library)
+        int kcs[bsk::kMaxForwardChunks];
+        const int nkc = base.prec == BSK_FP64 ? 1 : bsk::forward_chunks_f32(b, base.prec, base.kahan, base.rh, kcs);
+        if (base.prec == BSK_FP64) kcs[0] = 0;
+        for (int ik = 0; ik < nkc; ++ik) {
+            const int kc = kcs[ik];
             for (int S : rows) {
                 if (S > H && S != rows[0]) continue;
                 bsk_options c = o;
                 c.block = b;
                 c.strip_h = S;
-                c.order_chunk = base.prec == BSK_FP64 ? 0 : kc;
+                c.order_chunk = kc;
                 float ms_min = 1e30f;
                 for (int rep = 0; rep < 4; ++rep) {
                     if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) break;

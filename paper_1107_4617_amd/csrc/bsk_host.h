@@ -63,6 +63,8 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
 // the full one) and optionally a third size between them (0: none): the one
 // with the lower estimated cost for K orders.
 int pick_chunk(int K, int full, int small = 0, int mid = 0);
+// The cheapest of n pass sizes by the same cost.
+int pick_chunk_of(int K, const int *sizes, int n);
 // Plan of the polynomial range kernel, cached per (N, sigma_r, T, eps).
 std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, double eps);
 // Fills the launch arguments; the weights are padded with zeros to a multiple

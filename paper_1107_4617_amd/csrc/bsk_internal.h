@@ -215,6 +215,13 @@ bool valid_chunk_backward_f32(int block, int kc);
 // The 12-order pass of the 256-lane plain FP32 forward and adjoint (0 for
 // other lane counts).
 int mid_chunk_forward_f32(int block);
+// Every pass size of the FP32 forward for a block, stack (prec, kahan) and
+// horizontal radius rh: writes them to sizes (at most kMaxForwardChunks) and
+// returns how many.  The 256-lane plain stack has 8, 12 and 16 orders, and 20
+// and 24 at the compile-time radii; the others the full and the half pass.
+constexpr int kMaxForwardChunks = 5;
+int forward_chunks_f32(int block, int prec, int kahan, int rh, int *sizes);
+bool forward_chunk_ok_f32(int block, int prec, int kahan, int rh, int kc);
 int mid_chunk_backward_f32(int block);
 int big_chunk_backward_f32(int block);   // 0: none for this lane count
 int chunk_forward_f32(int block);

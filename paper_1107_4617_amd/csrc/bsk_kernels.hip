@@ -70,6 +70,34 @@ bool valid_chunk_backward_f32(int block, int kc)
 // forward, 166 for the adjoint), and orders counts such as 22 then take two
 // passes instead of three (or two padded ones of 16).
 int mid_chunk_forward_f32(int block) { return block == 256 ? 12 : 0; }
+// 20- and 24-order passes of the 256-lane plain FP32 forward at the
+// compile-time radii still fit three workgroups per CU (150 and 166 VGPRs, no
+// spill): many orders then take fewer passes, each of which repeats the
+// recurrence starts of every row and the round trip of the partial
+// accumulators through HBM.  (The run-time-radius R stage reads two prefixes
+// per channel, and its one-pass 24-order kernel spills.)
+int forward_chunks_f32(int block, int prec, int kahan, int rh, int *sizes)
+{
+    int n = 0;
+    sizes[n++] = kr_f32(block);
+    if (kr_f32(block) / 2 >= 1) sizes[n++] = kr_f32(block) / 2;
+    if (block == 256 && prec == 0 && !kahan) {
+        sizes[n++] = 12;
+        if (forward_radius_kernel(block, rh)) {
+            sizes[n++] = 20;
+            sizes[n++] = 24;
+        }
+    }
+    return n;
+}
+bool forward_chunk_ok_f32(int block, int prec, int kahan, int rh, int kc)
+{
+    int sizes[kMaxForwardChunks];
+    const int n = forward_chunks_f32(block, prec, kahan, rh, sizes);
+    for (int i = 0; i < n; ++i)
+        if (sizes[i] == kc) return true;
+    return false;
+}
 int mid_chunk_backward_f32(int block) { return block == 256 ? 12 : 0; }
 // A 24-order adjoint pass for 256-lane strips (two workgroups per CU, 239
 // VGPRs): 17 to 24 folded orders (N from 33 to 48) then take one pass instead
@@ -128,7 +156,9 @@ template <int QUANT, bool KAHAN>
 static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s, int *occ)
 {
     if constexpr (QUANT == 0 && !KAHAN) {
-        if (block == 256 && kc == mid_chunk_forward_f32(256)) return fwd32_mid(a, s, occ);
+        if (block == 256 && kc == 12) return fwd32_mid(a, s, occ);
+        // 20 and 24 orders: the compile-time radii only (forward_chunk_ok_f32)
+        if (block == 256 && (kc == 20 || kc == 24)) return launch_forward_f32_radius(a, kc, s, occ);
     }
     switch (block) {
     case 256: return fwd32_block<256, QUANT, KAHAN>(a, kc, s, occ);
@@ -140,8 +170,7 @@ static hipError_t fwd32(const StripArgs &a, int block, int kc, hipStream_t s, in
 
 hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, int kahan, hipStream_t s, int *occ)
 {
-    const bool mid = prec == 0 && !kahan && kc == mid_chunk_forward_f32(block);
-    if (!valid_chunk_forward_f32(block, kc) && !mid) return hipErrorInvalidValue;
+    if (!forward_chunk_ok_f32(block, prec, kahan, a.rh, kc)) return hipErrorInvalidValue;
     if (prec == 1) return kahan ? fwd32<1, true>(a, block, kc, s, occ) : fwd32<1, false>(a, block, kc, s, occ);
     if (prec == 2) return kahan ? fwd32<2, true>(a, block, kc, s, occ) : fwd32<2, false>(a, block, kc, s, occ);
     if (prec == 4) return kahan ? fwd32<4, true>(a, block, kc, s, occ) : fwd32<4, false>(a, block, kc, s, occ);

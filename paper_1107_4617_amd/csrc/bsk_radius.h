@@ -30,12 +30,14 @@ hipError_t fwd_radius_pass(const StripArgs &a, hipStream_t s, int *occ)
     return launch<float, 256, KR, KL, PolForward<float>, 0, false, 3, R>(a, s, occ);
 }
 
-// The three pass sizes of the 256-lane plain FP32 forward: 16, 12 and 8 orders.
+// The pass sizes of the 256-lane plain FP32 forward: 8, 12, 16, 20 and 24 orders.
 template <int R>
 hipError_t fwd_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
     static_assert(kr_f32(256) == 16 && kl_f32(256) == 4, "the pass sizes below are the 256-lane ones");
     switch (kc) {
+    case 24: return fwd_radius_pass<R, 24>(a, s, occ);
+    case 20: return fwd_radius_pass<R, 20>(a, s, occ);
     case 16: return fwd_radius_pass<R, 16>(a, s, occ);
     case 12: return fwd_radius_pass<R, 12>(a, s, occ);
     case 8: return fwd_radius_pass<R, 8>(a, s, occ);

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1107_4617_amd import bilateral, bilateral_batched, order_for
+from paper_1107_4617_amd import batched_shape, bilateral, bilateral_batched, order_for
 from paper_1107_4617_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -26,14 +26,15 @@ def _batch(n, seed, lo=20, hi=300):
 
 def test_batched_equals_single_image_path_and_oracle():
     specs, imgs = _batch(14, seed=41)
-    outs = bilateral_batched(imgs, [s[2] for s in specs], [s[3] for s in specs], T)
+    radii, sig = [s[2] for s in specs], [s[3] for s in specs]
+    outs = bilateral_batched(imgs, radii, sig, T)
     torch.cuda.synchronize()
-    for (H, W, r, sg, _), x, y in zip(specs, imgs, outs):
-        # same launch shape (256 lanes, 96-row units, the pass size both paths choose
-        # for the image's order count); the single-image path compiles a one-pass
-        # launch with its chain start mode as a constant, which may round differently
-        # (bound: about 30 FP32 rounding units of values up to 255)
-        single = bilateral(x, r, sg, T, block=256, strip_h=96)
+    blk, rows, chunks = batched_shape([(s[0], s[1]) for s in specs], radii, sig, T)
+    for (H, W, r, sg, _), x, y, rw, kc in zip(specs, imgs, outs, rows, chunks):
+        # same launch shape (lanes, rows per unit and pass size); the single-image path
+        # compiles a one-pass launch with its chain start mode as a constant, which may
+        # round differently (bound: about 30 FP32 rounding units of values up to 255)
+        single = bilateral(x, r, sg, T, block=blk, strip_h=rw, order_chunk=kc)
         torch.cuda.synchronize()
         assert float((single - y).abs().max()) <= 5e-4
     for b in (0, 5, 13):
@@ -71,10 +72,13 @@ def test_full_batch_256_images():
     bilateral_batched(imgs, radii, sig, T, outs=outs)
     torch.cuda.synchronize()
     assert all(bool(torch.isfinite(o).all()) for o in outs)
+    blk, rows, chunks = batched_shape([(s[0], s[1]) for s in specs], radii, sig, T)
     rng = np.random.default_rng(4)
     for b in rng.choice(256, 6, replace=False):
         H, W, r, sg, _ = specs[b]
-        single = bilateral(imgs[b], r, sg, T, block=256, strip_h=96)
+        # the batched kernel's shape for this image (the single-image path alone would
+        # also take 20- and 24-order passes, which round differently)
+        single = bilateral(imgs[b], r, sg, T, block=blk, strip_h=rows[b], order_chunk=chunks[b])
         torch.cuda.synchronize()
         assert float((single - outs[b]).abs().max()) <= 5e-4
         f = imgs[b].cpu().numpy()

@@ -151,14 +151,59 @@ def test_compile_time_radius_kernels_multi_pass(r, N, sigma):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
-@pytest.mark.parametrize("kc", [8, 12, 16])
-def test_every_pass_size(kc):
-    """30 folded orders (N = 59) in passes of 8, 12 or 16 orders (4, 3 or 2 passes, the last
-    one padded) against the oracle."""
+@pytest.mark.parametrize("r,kc", [(7, 8), (7, 12), (7, 16), (7, 20), (7, 24),
+                                  (40, 8), (40, 12), (40, 16)])
+def test_every_pass_size(kc, r):
+    """30 folded orders (N = 59) in passes of 8, 12, 16, 20 or 24 orders (4, 3, 2, 2 or 2
+    passes, the last one padded) against the oracle: every pass size of the compile-time
+    radius 7, and those of the run-time radius 40."""
     f = wl.rect_image(100, 300, seed=59, n_rect=10)
-    ref = oracle.bilateral(f, 7, 22.0, 59)
-    out = _gpu_filter(f, 7, 22.0, N=59, block=256, order_chunk=kc)
+    ref = oracle.bilateral(f, r, 22.0, 59)
+    out = _gpu_filter(f, r, 22.0, N=59, block=256, order_chunk=kc)
     assert np.max(np.abs(out - ref)) <= TOL32
+
+
+@pytest.mark.parametrize("kc", [20, 24])
+def test_large_passes_need_a_compile_time_radius(kc):
+    """The 20- and 24-order passes exist at the radii 1 to 32 only; elsewhere the request is
+    rejected before any launch."""
+    from paper_1107_4617_amd._lib import BskError
+
+    f = wl.rect_image(40, 300, seed=1, n_rect=4)
+    with pytest.raises(BskError, match="EINVAL"):
+        _gpu_filter(f, 40, 22.0, N=59, block=256, order_chunk=kc)
+
+
+@pytest.mark.parametrize("r,N", [(20, 43), (20, 44), (31, 43), (2, 44)])
+def test_one_pass_of_24(r, N):
+    """22 or 23 folded orders: the automatic choice is one 24-order pass with the start mode
+    as a constant (odd and even N)."""
+    f = wl.rect_image(90, 330, seed=N + r, n_rect=10)
+    ref = oracle.bilateral(f, r, 25.0, N)
+    out = _gpu_filter(f, r, 25.0, N=N)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
+def test_autotune_applies_its_shape(tmp_path):
+    """bsk_autotune times the single-image launch shapes (lanes, rows, every pass size),
+    caches the fastest, and a later call with automatic options runs exactly that shape:
+    bit for bit the output of the call that names it, within the oracle bound."""
+    from paper_1107_4617_amd import autotune, tune_cache_clear
+
+    tune_cache_clear()
+    try:
+        f = wl.rect_image(96, 500, seed=5, n_rect=10)
+        x = torch.from_numpy(f).cuda()
+        b, rows, kc, ms = autotune(x, 6, 12.0, T, path=str(tmp_path / "tune.jsonl"))
+        assert b in (256, 512, 1024) and rows > 0 and kc > 0 and ms > 0
+        auto = bilateral(x, 6, 12.0, T)
+        named = bilateral(x, 6, 12.0, T, block=b, strip_h=rows, order_chunk=kc)
+        torch.cuda.synchronize()
+        assert torch.equal(auto, named)
+        ref = oracle.bilateral(f, 6, 12.0, order_for(12.0, T))
+        assert np.max(np.abs(auto.cpu().numpy() - ref)) <= TOL32
+    finally:
+        tune_cache_clear()
 
 
 def test_radius_zero_is_exact_identity():
