@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1107_4617_amd import batched_shape, bilateral, bilateral_batched, order_for
+from paper_1107_4617_amd import batched_shape, bilateral, bilateral_batched, order_for, plan_info
 from paper_1107_4617_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -24,6 +24,20 @@ def _batch(n, seed, lo=20, hi=300):
     return specs, imgs
 
 
+def _same_as_single_image(single, y, sigma_r, kc):
+    """The batched output against the single-image path at the same launch shape (lanes,
+    rows per unit, pass size).  With several passes both run the same arithmetic: equal bit
+    for bit.  In one pass the single-image path takes its chain start mode as a constant,
+    and its recurrences drift from those of the general start by up to about 130 FP32
+    rounding units of values up to 255 over 20 orders (measured: up to 4.6e-4 at 16 orders,
+    1.2e-3 at 20)."""
+    K = plan_info(order_for(sigma_r, T))[0]
+    if K > kc:
+        assert torch.equal(single, y), (K, kc)
+    else:
+        assert float((single - y).abs().max()) <= 2e-3, (K, kc)
+
+
 def test_batched_equals_single_image_path_and_oracle():
     specs, imgs = _batch(14, seed=41)
     radii, sig = [s[2] for s in specs], [s[3] for s in specs]
@@ -31,12 +45,9 @@ def test_batched_equals_single_image_path_and_oracle():
     torch.cuda.synchronize()
     blk, rows, chunks = batched_shape([(s[0], s[1]) for s in specs], radii, sig, T)
     for (H, W, r, sg, _), x, y, rw, kc in zip(specs, imgs, outs, rows, chunks):
-        # same launch shape (lanes, rows per unit and pass size); the single-image path
-        # compiles a one-pass launch with its chain start mode as a constant, which may
-        # round differently (bound: about 30 FP32 rounding units of values up to 255)
         single = bilateral(x, r, sg, T, block=blk, strip_h=rw, order_chunk=kc)
         torch.cuda.synchronize()
-        assert float((single - y).abs().max()) <= 5e-4
+        _same_as_single_image(single, y, sg, kc)
     for b in (0, 5, 13):
         H, W, r, sg, _ = specs[b]
         ref = oracle.bilateral(imgs[b].cpu().numpy(), r, sg, order_for(sg, T))
@@ -76,11 +87,11 @@ def test_full_batch_256_images():
     rng = np.random.default_rng(4)
     for b in rng.choice(256, 6, replace=False):
         H, W, r, sg, _ = specs[b]
-        # the batched kernel's shape for this image (the single-image path alone would
-        # also take 20- and 24-order passes, which round differently)
+        # the batched kernel's shape for this image (alone, the single-image path would
+        # take other pass sizes)
         single = bilateral(imgs[b], r, sg, T, block=blk, strip_h=rows[b], order_chunk=chunks[b])
         torch.cuda.synchronize()
-        assert float((single - outs[b]).abs().max()) <= 5e-4
+        _same_as_single_image(single, outs[b], sg, chunks[b])
         f = imgs[b].cpu().numpy()
         idx = rng.integers(0, H * W, 400)
         ref = oracle.bilateral_at(f, idx, r, sg, order_for(sg, T))
@@ -120,7 +131,7 @@ def test_autotuned_shapes_are_applied(tmp_path):
         for i, (H, W, r, sg, _) in enumerate(specs):
             single = bilateral(imgs[i], r, sg, T, block=blk, strip_h=rows[i], order_chunk=chunk[i])
             torch.cuda.synchronize()
-            assert float((single - outs[i]).abs().max()) <= 5e-4, i
+            _same_as_single_image(single, outs[i], sg, chunk[i])
             if i % 3 == 0:
                 idx = rng.integers(0, H * W, 300)
                 ref = oracle.bilateral_at(imgs[i].cpu().numpy(), idx, r, sg, order_for(sg, T))

@@ -19,15 +19,14 @@ def _n0(sigma, T=255.0):
     return math.ceil((2 * T / (math.pi * sigma)) ** 2)
 
 
-def _default_chunk(K, full=16, mid=12):
-    # the pass size with the lower estimated cost, as the library picks it (ties keep the
-    # full pass, then the half pass)
+def _default_chunk(K, sizes=(16, 8, 12)):
+    # the pass size with the lowest estimated cost, as the library picks it (ties keep the
+    # earlier size: the full pass, its half, then 12 orders)
     cost = lambda kc: ((K + kc - 1) // kc) * (kc + 5.0 + 0.1 * kc)  # noqa: E731
-    best = full
-    if cost(full // 2) < cost(best):
-        best = full // 2
-    if mid and cost(mid) < cost(best):
-        best = mid
+    best = sizes[0]
+    for kc in sizes[1:]:
+        if cost(kc) < cost(best):
+            best = kc
     return best
 
 
