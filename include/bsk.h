@@ -100,7 +100,8 @@ typedef struct {
                              1024: 4|2 (lanes: full|half); adjoint 256: 24|16|12|8, 512: 8|4,
                              1024: 2|1; batched 256: 16|12|8, 512: 8|4, 1024: 4|2; spatial kernel 4|2
                              (one frequency) or 2|1; polynomial range kernel (channel pairs)
-                             256 and 512: 16|8, 1024: 8|4; ignored by FP64 and the training
+                             256: 24|16|8 (24 at the radii 3, 5, 8, 10, 16, 20, 25, 32), 512:
+                             16|8, 1024: 8|4; ignored by FP64 and the training
                              forward; 0 = automatic (the cheaper for the order count) */
     /* Spatial kernel (Algorithms 1 and 2 with M > 1; Section 3, separable
      * kernels): 0 = the box; Ns in 1..6 = the separable raised cosine

@@ -163,7 +163,7 @@ std::shared_ptr<const bsk::PolyPlan> poly_plan(int N, double sigma_r, double T, 
 // and, when there are several passes, the equivalent of about 250 for the
 // workspace traffic (48 bytes per pixel); the first pass also runs the
 // recurrence from d_2N down to its channels.
-static int pick_chunk_poly(int pairs, int N, int full)
+static int pick_chunk_poly(int pairs, int N, int full, int big)
 {
     auto cost = [&](int kc) {
         const int np = (pairs + kc - 1) / kc * kc;
@@ -172,7 +172,9 @@ static int pick_chunk_poly(int pairs, int N, int full)
         c += 7.0 * std::max(0, 2 * N - 2 * np);
         return c;
     };
-    return cost(full / 2) < cost(full) ? full / 2 : full;
+    int kc = cost(full / 2) < cost(full) ? full / 2 : full;
+    if (big > 0 && cost(big) < cost(kc)) kc = big;
+    return kc;
 }
 
 // Workgroups per compute unit of the kernel a resolved request will launch.
@@ -363,13 +365,14 @@ int resolve(int H, int W, int radius, float sigma_r, float T, const bsk_options 
             kc = bsk::chunk_poly_f64(block);
         } else {
             const int full = bsk::chunk_poly_f32(block);
+            const int big = bsk::big_chunk_poly_f32(block, r->rh);
             if (o.order_chunk) {
-                if (o.order_chunk != full && o.order_chunk != full / 2)
-                    return fail(BSK_EINVAL, "order_chunk %d is not a polynomial-kernel pass size (%d or %d)",
-                                o.order_chunk, full, full / 2);
+                if (o.order_chunk != full && o.order_chunk != full / 2 && !(big && o.order_chunk == big))
+                    return fail(BSK_EINVAL, "order_chunk %d is not a polynomial-kernel pass size (%d or %d%s)",
+                                o.order_chunk, full, full / 2, big ? ", or 24 at this radius" : "");
                 kc = o.order_chunk;
             } else {
-                kc = pick_chunk_poly(r->poly_pairs, r->N, full);
+                kc = pick_chunk_poly(r->poly_pairs, r->N, full, big);
             }
         }
     } else if (spatial) {

@@ -169,6 +169,9 @@ struct PolyArgs {
 hipError_t launch_poly_f32(const PolyArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 hipError_t launch_poly_f64(const PolyArgs &a, int block, hipStream_t s, int *occ = nullptr);
 int chunk_poly_f32(int block);   // pairs per full pass (the half pass has half)
+// The 24-pair pass of the FP32 polynomial kernel (256 lanes at its compile-time
+// radii 3, 5, 8, 10, 16, 20, 25 and 32), else 0.
+int big_chunk_poly_f32(int block, int rh);
 int chunk_poly_f64(int block);
 
 // Launch helpers implemented in bsk_kernels.hip.  `prec` selects the stack

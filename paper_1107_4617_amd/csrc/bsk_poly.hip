@@ -485,12 +485,40 @@ static hipError_t poly32_radius(const PolyArgs &a, hipStream_t s, int *occ)
     }
 }
 
+// The 24-pair pass of 256 lanes, at those radii only: 158 VGPRs and three
+// workgroups per CU (the run-time-radius kernel of that size spills), so many
+// channel pairs take fewer passes.
+constexpr int kbig_poly_f32 = 24;
+bool big_chunk_poly_ok(int block, int rh)
+{
+    switch (rh) {
+    case 3: case 5: case 8: case 10: case 16: case 20: case 25: case 32: return block == 256;
+    default: return false;
+    }
+}
+static hipError_t poly32_big(const PolyArgs &a, hipStream_t s, int *occ)
+{
+    constexpr int KR = kbig_poly_f32, KL = kl_poly_f32(256);
+    switch (a.rh) {
+    case 3: return poly_launch<float, 256, KR, KL, 3>(a, s, occ);
+    case 5: return poly_launch<float, 256, KR, KL, 5>(a, s, occ);
+    case 8: return poly_launch<float, 256, KR, KL, 8>(a, s, occ);
+    case 10: return poly_launch<float, 256, KR, KL, 10>(a, s, occ);
+    case 16: return poly_launch<float, 256, KR, KL, 16>(a, s, occ);
+    case 20: return poly_launch<float, 256, KR, KL, 20>(a, s, occ);
+    case 25: return poly_launch<float, 256, KR, KL, 25>(a, s, occ);
+    case 32: return poly_launch<float, 256, KR, KL, 32>(a, s, occ);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int BLOCK>
 static hipError_t poly32_block(const PolyArgs &a, int kc, hipStream_t s, int *occ)
 {
     constexpr int KR = kr_poly_f32(BLOCK), KL = kl_poly_f32(BLOCK);
     constexpr int KLH = KL < KR / 2 ? KL : KR / 2;
     if constexpr (BLOCK == 256) {
+        if (kc == kbig_poly_f32) return poly32_big(a, s, occ);
         if (kc == KR) return poly32_radius<KR, KL>(a, s, occ);
         if (kc == KR / 2) return poly32_radius<KR / 2, KLH>(a, s, occ);
     }
@@ -500,6 +528,7 @@ static hipError_t poly32_block(const PolyArgs &a, int kc, hipStream_t s, int *oc
 }
 
 int chunk_poly_f32(int block) { return block == 1024 ? kr_poly_f32(1024) : kr_poly_f32(256); }
+int big_chunk_poly_f32(int block, int rh) { return big_chunk_poly_ok(block, rh) ? kbig_poly_f32 : 0; }
 int chunk_poly_f64(int block)
 {
     return block == 256 ? kr_poly_f64(256) : block == 512 ? kr_poly_f64(512) : kr_poly_f64(1024);

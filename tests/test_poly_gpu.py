@@ -113,12 +113,21 @@ def test_poly_truncated_within_bound(sigma_r, eps):
     assert np.all(np.abs(out - ref) <= TOL32 + bound)
 
 
-def test_poly_half_pass_matches_full():
+@pytest.mark.parametrize("kc", [8, 16, 24])
+def test_poly_every_pass_size(kc):
+    """38 channel pairs (N = 37) in passes of 8, 16 or 24 pairs (5, 3 or 2 passes) at a radius
+    with its own kernels."""
     f = wl.rect_image(60, 200, seed=6)
-    a = _run(f, 5, 30.0, order_chunk=16)
-    b = _run(f, 5, 30.0, order_chunk=8)
+    a = _run(f, 5, 30.0, order_chunk=kc)
     ref = oracle.bilateral_poly(f, 5, 30.0, 37)
-    assert np.max(np.abs(a - ref)) <= TOL32 and np.max(np.abs(b - ref)) <= TOL32
+    assert np.max(np.abs(a - ref)) <= TOL32
+
+
+def test_poly_24_pair_pass_needs_its_radii():
+    """The 24-pair pass exists at the polynomial kernel's compile-time radii only."""
+    f = wl.rect_image(30, 200, seed=6)
+    with pytest.raises(_lib.BskError, match="EINVAL"):
+        _run(f, 6, 30.0, order_chunk=24)
 
 
 def test_poly_offset_data():
