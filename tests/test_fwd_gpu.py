@@ -163,6 +163,17 @@ def test_every_pass_size(kc, r):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
+@pytest.mark.parametrize("r", [5, 40])
+def test_many_orders(r):
+    """sigma_r = 10 (N_0 = 264, 133 folded orders): six 24-order passes at the compile-time
+    radius 5, nine 16-order ones at the run-time radius 40."""
+    f = wl.rect_image(48, 300, seed=264 + r, n_rect=8)
+    N = order_for(10.0, T)
+    ref = oracle.bilateral(f, r, 10.0, N)
+    out = _gpu_filter(f, r, 10.0, strip_h=17)
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
 @pytest.mark.parametrize("kc", [20, 24])
 def test_large_passes_need_a_compile_time_radius(kc):
     """The 20- and 24-order passes exist at the radii 1 to 32 only; elsewhere the request is
