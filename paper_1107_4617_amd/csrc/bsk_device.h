@@ -1276,12 +1276,14 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         if constexpr (FOLDV) {
                             // the prefixes of order m scaled by its weight v_m
                             const AT vw = vH[floormod(h - 1, NSUB)];
-                            // a multiply-add with a zero addend is the rounded product, and
-                            // keeps the compiler from fusing it into the box subtraction
-                            // below (E(p) - E(p - D) at u = 0): the box sums are then the
-                            // same subtractions of the same prefix values that the
-                            // run-time-radius kernels make in their R stage
-                            const AT offv = fmat(off, vw, AT(0));
+                            // box-sum walkers: a multiply-add with a zero addend is the
+                            // rounded product, and keeps the compiler from fusing it into
+                            // the box subtraction below (E(p) - E(p - D) at u = 0), so the
+                            // box sums are the same subtractions of the same prefix values
+                            // that the run-time-radius kernels make in their R stage
+                            AT offv;
+                            if constexpr (WBOX) offv = fmat(off, vw, AT(0));
+                            else offv = off * vw;
                             if constexpr (WBOX) {
                                 // position p = G w + u: E(p - D), D = 2 rh + 1, is element
                                 // u - D mod G of walker w - QS (u >= DR) or of walker
