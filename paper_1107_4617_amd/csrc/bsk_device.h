@@ -552,6 +552,12 @@ template <int SM>
 struct FoldsWeight<PolTrain<SM>> {
     static constexpr bool value = true;
 };
+// the two-pixel patch's weight table (w1[g] v_m per packed order) scales the
+// walker rows the same way
+template <int G>
+struct FoldsWeight<PolPatch2G<G>> {
+    static constexpr bool value = true;
+};
 
 // Backward (adjoint): with alpha = gbar / Q and ut = u - ref, channels
 // (alpha C, alpha S, alpha ut C, alpha ut S); one accumulator
@@ -956,7 +962,9 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
     // (order k, pair, horizontal basis row, member), NCH NB rows per order.
     // When the rows of one wavefront all belong to one order the index is made
     // wave-uniform, so that the weights come from scalar loads.
-    constexpr bool FOLDV = FoldsWeight<POL>::value;
+    // (the patch kernels fold their weights only where the walkers form box
+    // sums: with the run-time radius the fold measured 0.7% slower there)
+    constexpr bool FOLDV = FoldsWeight<POL>::value && (!IsPatch2<POL>::value || RHC > 0);
     constexpr int RPW = 64 / CH;   // walker rows per wavefront
     int kw = min(wrow, ROWS - 1) / (NCH * NB);
     if constexpr (RPW <= NCH * NB && (NCH * NB) % RPW == 0) kw = __builtin_amdgcn_readfirstlane(kw);
@@ -995,7 +1003,11 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
         // weights of the walker rows of each sub-phase (FOLDV)
         AT vH[FOLDV ? NSUB : 1];
 #pragma unroll
-        for (int s = 0; s < (FOLDV ? NSUB : 1); ++s) vH[s] = FOLDV ? weight<AT>(gm, m0 + s * KL + kw) : AT(1);
+        for (int s = 0; s < (FOLDV ? NSUB : 1); ++s) {
+            if constexpr (!FOLDV) vH[s] = AT(1);
+            else if constexpr (IsPatch2<POL>::value) vH[s] = ((ConstPtr<float>)gm.p2_vf)[m0 + s * KL + kw];
+            else vH[s] = weight<AT>(gm, m0 + s * KL + kw);
+        }
 
         AT V[KR][NCH];
         AT Cmp[KAHAN ? KR : 1][NCH];
@@ -1237,8 +1249,8 @@ __device__ __forceinline__ void strip_body(const IO &a, const Geom &gm, int bx, 
                         }
                         chain_restart<POL>(cc, m);
                         AT v;
-                        if constexpr (IsPatch2<POL>::value) v = ((ConstPtr<float>)gm.p2_vf)[m0 + m];
-                        else if constexpr (FOLDV) v = AT(1);   // already in B
+                        if constexpr (FOLDV) v = AT(1);   // already in B
+                        else if constexpr (IsPatch2<POL>::value) v = ((ConstPtr<float>)gm.p2_vf)[m0 + m];
                         else v = weight<AT>(gm, m0 + m);
                         const AT vom = v * (om0 + (AT)m * dlt);
                         if constexpr (CSTART == 0) {

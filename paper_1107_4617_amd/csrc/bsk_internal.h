@@ -201,6 +201,10 @@ hipError_t launch_backward_f32(const StripArgs &a, int block, int kc, float *gra
 constexpr int kPatchPackPass = 16;
 constexpr int kPatchPackMax = 8;
 hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, int pack, hipStream_t s, int *occ = nullptr);
+// The patch kernels with the radius as a compile-time constant
+// (bsk_patch_radius.hip): whether block, kc and rh have them, and the launch.
+bool patch_radius_kernel(int block, int kc, int rh);
+hipError_t launch_patch2_f32_radius(const StripArgs &a, int pack, hipStream_t s, int *occ = nullptr);
 // FP32 forward with the separable spatial kernel of plan sp (nsc >= 1).
 hipError_t launch_spatial_f32(const StripArgs &a, int block, const SpatialPlan &sp, int kc, hipStream_t s,
                               int *occ = nullptr);

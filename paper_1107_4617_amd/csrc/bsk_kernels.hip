@@ -208,10 +208,12 @@ hipError_t launch_patch2_f32(const StripArgs &a, int block, int kc, int pack, hi
     if (pack != 0) {
         if (block != 256 || kc != kPatchPackPass || pack < 1 || pack > kPatchPackMax) return hipErrorInvalidValue;
         if (!occ && (!a.vf_dev || a.K % kc != 0)) return hipErrorInvalidValue;
+        if (patch_radius_kernel(block, kc, a.rh)) return launch_patch2_f32_radius(a, pack, s, occ);
         return patch2_packed<kPatchPackMax>(a, pack, s, occ);
     }
     if (!occ && (!a.vf_dev || a.p2_group < kc || a.p2_group % kc != 0 || a.K % a.p2_group != 0))
         return hipErrorInvalidValue;
+    if (patch_radius_kernel(block, kc, a.rh)) return launch_patch2_f32_radius(a, 0, s, occ);
     switch (block) {
     case 256: return patch2_block<256>(a, kc, s, occ);
     case 512: return patch2_block<512>(a, kc, s, occ);

@@ -69,6 +69,17 @@ def test_nlm2_matches_oracle(shape, r, s1, s2, off, N1, N2, kw):
     assert np.max(err) <= TOL32, (np.max(err), np.unravel_index(np.argmax(err), err.shape))
 
 
+@pytest.mark.parametrize("r", [8, 20, 32])
+@pytest.mark.parametrize("N2", [2, 8, 14, 30])   # packed 8, 3 and 2 groups per pass; unpacked
+def test_nlm2_compile_time_radius_kernels(r, N2):
+    """The radii with their own patch kernels (the walkers hand out weighted box sums), packed
+    and unpacked, over two strips and several segments."""
+    f = wl.rect_image(40, 300, seed=7 * r + N2)
+    out = _run(f, r, 60.0, 60.0, (1, -1), 8, N2, strip_h=13)
+    ref = oracle.nlm2(f, r, 60.0, 8, 60.0, N2, (1, -1))
+    assert np.max(np.abs(out - ref)) <= TOL32
+
+
 def test_nlm2_second_order_zero_matches_bilateral_path():
     """N2 = 0 is the bilateral filter: the two HIP paths agree to FP32 rounding."""
     f = wl.rect_image(70, 90, seed=4)
