@@ -630,7 +630,8 @@ struct PolBackward {
     {
         acc[0] = fmat(v * C, B[0], acc[0]);
     }
-    // E1 and E2 of the output pixel, loaded when its row's R stage starts
+    // E1 and E2 of an output pixel, read only by its finalisation (the strip
+    // body loads them a row ahead)
     template <typename AT>
     __device__ static void fetch_centre(const IO &a, int i, int j, AT *ctr)
     {
