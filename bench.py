@@ -44,6 +44,9 @@ BYTES_PER_PX = 8              # FP32 in + FP32 out; the stack never reaches HBM
 HEADLINE_KERNEL = "strip_kernel<float,256,16,4,PolForward<float,0>,0,false,3,20>"
 HEADLINE_HBM_BYTES = 282.7e6
 HEADLINE_VALU_INSTS = 194.15e6
+# SQ_LDS_IDX_ACTIVE per launch (cycles summed over the CUs in which the LDS
+# serves this kernel's accesses), from the same profile
+HEADLINE_LDS_ACTIVE = 144.648e6
 # VALU issue: one wave64 instruction per SIMD every 4 cycles (16 lanes, no
 # packed FP32), 4 SIMDs per CU, 256 CUs at 2.4 GHz
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
@@ -342,6 +345,10 @@ def main():
         rl["valu_lane_instructions_per_pixel_order"] = round(HEADLINE_VALU_INSTS * 64 / (px * K), 2)
     else:
         rl["valu_busy"] = None
+    # share of the launch during which the CUs' LDS is busy with the kernel's accesses
+    # (timing probes with LDS traffic removed show the launch time following it)
+    rl["lds_busy"] = (round(HEADLINE_LDS_ACTIVE / (256 * 2.4e9) / (mean_ms * 1e-3), 4)
+                      if HEADLINE_LDS_ACTIVE is not None else None)
     # Errors of each variant below against the FP64 oracle, evaluated in the CPU-baseline leg:
     # 100,000 seeded random pixels plus the 2,000 where the variant departs most from the
     # plain FP32 output.
