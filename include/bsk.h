@@ -96,7 +96,7 @@ typedef struct {
     int strip_h;          /* output rows per workgroup; 0 = auto */
     int order_chunk;      /* orders per pass, one of the pass sizes of the kernel that runs:
                              FP32 forward 256: 24|20|16|12|8 (12: plain FP32 stack only; 24
-                             and 20: plain FP32 stack at radii 1 to 32), 512: 8|4,
+                             and 20: plain FP32 stack at radii 1 to 64), 512: 8|4,
                              1024: 4|2 (lanes: full|half); adjoint 256: 24|16|12|8, 512: 8|4,
                              1024: 2|1; batched 256: 16|12|8, 512: 8|4, 1024: 4|2; spatial kernel 4|2
                              (one frequency) or 2|1; polynomial range kernel (channel pairs)
@@ -142,8 +142,9 @@ typedef struct {
  *   T > 0:  range bound, selects N_0
  * Runs on the default stream and synchronises before returning.
  * Performance: with 256-lane strips (the default for r <= 64) every radius
- * from 1 to 32 runs kernels compiled for that radius in the plain FP32
- * forward and in the training forward and adjoint below, and the radii 3, 5,
+ * from 1 to 64 runs kernels compiled for that radius in the plain FP32
+ * forward, every radius from 1 to 32 in the training forward and adjoint
+ * below, and the radii 3, 5,
  * 8, 10, 16, 20, 25 and 32 also in the q_2 spatial kernel, the FP32
  * polynomial kernel and the two-pixel patch's 16-order pass.  They are 3-9%
  * faster than the run-time-radius kernels

@@ -11,6 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsk.so")
 # the largest sources first, so the parallel build finishes sooner
 SOURCES = ["bsk_radius_1_8.hip", "bsk_radius_9_16.hip", "bsk_radius_17_24.hip", "bsk_radius_25_32.hip",
+           "bsk_radius_33_40.hip", "bsk_radius_41_48.hip", "bsk_radius_49_56.hip", "bsk_radius_57_64.hip",
            "bsk_kernels.hip", "bsk_poly.hip", "bsk_patch_radius.hip", "bsk_radius.hip", "bsk_batched.hip", "bsk_noalloc.hip", "bsk_plan.cpp",
            "bsk_api.cpp", "bsk_batched.cpp"]
 

@@ -182,12 +182,13 @@ hipError_t launch_forward_f32(const StripArgs &a, int block, int kc, int prec, i
                               int *occ = nullptr);
 hipError_t launch_forward_f64(const StripArgs &a, int block, int kc, hipStream_t s, int *occ = nullptr);
 // Plain FP32 forward kernels with the radius as a compile-time constant (256
-// lanes, radii 1 to 32; bsk_radius.h): whether block and rh have them, and the
-// launch (kc one of the 256-lane pass sizes 16, 12 and 8; one pass or several).
+// lanes, radii 1 to 64; bsk_radius.h): whether block and rh have them, and the
+// launch (kc one of the 256-lane pass sizes 8, 12, 16, 20 and 24; one pass or
+// several).
 bool forward_radius_kernel(int block, int rh);
 hipError_t launch_forward_f32_radius(const StripArgs &a, int kc, hipStream_t s, int *occ = nullptr);
 // The training forward (8-order pass) and the adjoint (24-, 16- and 8-order
-// passes) with the same compile-time radii.
+// passes) with the radius as a compile-time constant (radii 1 to 32).
 bool train_radius_kernel(int block, int rh);
 bool backward_radius_kernel(int block, int rh, int kc);
 hipError_t launch_train_f32_radius(const StripArgs &a, hipStream_t s, int *occ = nullptr);

@@ -1,14 +1,15 @@
-// The 256-lane plain FP32 forward, training forward and adjoint with the box
-// radius as a compile-time constant, for every radius 1 to 32.  Their walkers
+// The 256-lane plain FP32 forward (every radius 1 to 64, all that 256-lane
+// strips take by default), training forward and adjoint (radii 1 to 32) with
+// the box radius as a compile-time constant.  Their walkers
 // hand box sums to the R stage instead of prefix sums (strip_body, RHC > 0),
 // which halves the R stage's LDS reads: the forward's R stage reads four
 // channels per order, the training forward's six and the adjoint's four.
 // Other radii, the 16-bit and compensated stacks use the run-time-radius
 // kernels of bsk_kernels.hip.
 //
-// The radii are compiled in four parts of eight (bsk_radius_1_8.hip ...
-// bsk_radius_25_32.hip), so the build compiles them in parallel; bsk_radius.hip
-// picks the part.
+// The radii are compiled in parts of eight (bsk_radius_1_8.hip ...
+// bsk_radius_57_64.hip; the parts above 32 hold the forward only), so the build
+// compiles them in parallel; bsk_radius.hip picks the part.
 #pragma once
 #include <utility>
 
@@ -16,7 +17,8 @@
 
 namespace bsk {
 
-constexpr int kRadiusCtMax = 32;      // compile-time radii 1 .. kRadiusCtMax
+constexpr int kRadiusCtMax = 32;       // training forward and adjoint: radii 1 .. kRadiusCtMax
+constexpr int kRadiusCtMaxFwd = 64;    // forward: radii 1 .. kRadiusCtMaxFwd
 constexpr int kRadiusPerPart = 8;
 
 // One pass with the start mode as a constant (K <= KR), else passes with the
@@ -110,7 +112,7 @@ hipError_t backward_radii(const StripArgs &a, int kc, hipStream_t s, int *occ)
                            std::make_integer_sequence<int, kRadiusPerPart>{});
 }
 
-// The part files' entry points (radii 1-8, 9-16, 17-24, 25-32).
+// The part files' entry points (radii 1-8, 9-16, 17-24, 25-32: all three families).
 #define BSK_RADIUS_PART_DECL(LO, HI)                                                                    \
     hipError_t forward_radius_##LO##_##HI(const StripArgs &a, int kc, hipStream_t s, int *occ);          \
     hipError_t train_radius_##LO##_##HI(const StripArgs &a, hipStream_t s, int *occ);                    \
@@ -120,5 +122,10 @@ BSK_RADIUS_PART_DECL(9, 16)
 BSK_RADIUS_PART_DECL(17, 24)
 BSK_RADIUS_PART_DECL(25, 32)
 #undef BSK_RADIUS_PART_DECL
+// the forward-only parts (radii 33-40, 41-48, 49-56, 57-64)
+hipError_t forward_radius_33_40(const StripArgs &a, int kc, hipStream_t s, int *occ);
+hipError_t forward_radius_41_48(const StripArgs &a, int kc, hipStream_t s, int *occ);
+hipError_t forward_radius_49_56(const StripArgs &a, int kc, hipStream_t s, int *occ);
+hipError_t forward_radius_57_64(const StripArgs &a, int kc, hipStream_t s, int *occ);
 
 }  // namespace bsk

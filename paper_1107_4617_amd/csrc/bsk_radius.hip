@@ -7,10 +7,11 @@ namespace bsk {
 namespace {
 
 bool radius_ct(int block, int rh) { return block == 256 && rh >= 1 && rh <= kRadiusCtMax; }
+bool radius_ct_fwd(int block, int rh) { return block == 256 && rh >= 1 && rh <= kRadiusCtMaxFwd; }
 
 }  // namespace
 
-bool forward_radius_kernel(int block, int rh) { return radius_ct(block, rh); }
+bool forward_radius_kernel(int block, int rh) { return radius_ct_fwd(block, rh); }
 bool train_radius_kernel(int block, int rh) { return radius_ct(block, rh); }
 bool backward_radius_kernel(int block, int rh, int kc)
 {
@@ -19,13 +20,17 @@ bool backward_radius_kernel(int block, int rh, int kc)
 
 hipError_t launch_forward_f32_radius(const StripArgs &a, int kc, hipStream_t s, int *occ)
 {
-    static_assert(kRadiusCtMax == 4 * kRadiusPerPart, "four parts of radii");
-    if (!radius_ct(256, a.rh)) return hipErrorInvalidValue;
+    static_assert(kRadiusCtMax == 4 * kRadiusPerPart && kRadiusCtMaxFwd == 8 * kRadiusPerPart, "parts of radii");
+    if (!radius_ct_fwd(256, a.rh)) return hipErrorInvalidValue;
     switch ((a.rh - 1) / kRadiusPerPart) {
     case 0: return forward_radius_1_8(a, kc, s, occ);
     case 1: return forward_radius_9_16(a, kc, s, occ);
     case 2: return forward_radius_17_24(a, kc, s, occ);
-    default: return forward_radius_25_32(a, kc, s, occ);
+    case 3: return forward_radius_25_32(a, kc, s, occ);
+    case 4: return forward_radius_33_40(a, kc, s, occ);
+    case 5: return forward_radius_41_48(a, kc, s, occ);
+    case 6: return forward_radius_49_56(a, kc, s, occ);
+    default: return forward_radius_57_64(a, kc, s, occ);
     }
 }
 

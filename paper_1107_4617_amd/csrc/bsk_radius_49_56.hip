@@ -1,0 +1,11 @@
+// Compile-time-radius forward kernels for the radii 49 to 56 (bsk_radius.h).
+#include "bsk_radius.h"
+
+namespace bsk {
+
+hipError_t forward_radius_49_56(const StripArgs &a, int kc, hipStream_t s, int *occ)
+{
+    return forward_radii<49>(a, kc, s, occ);
+}
+
+}  // namespace bsk

@@ -128,10 +128,10 @@ def test_compile_time_radius_kernels(r, N, sigma):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
-@pytest.mark.parametrize("r", range(1, 33))
+@pytest.mark.parametrize("r", range(1, 65))
 def test_every_compile_time_radius(r):
-    """Every radius from 1 to 32 has its own kernel: the headline's order count on a
-    small image with two strips and ragged segments."""
+    """Every radius from 1 to 64 has its own forward kernel: the headline's order count on
+    a small image with two or more strips and ragged segments."""
     f = wl.rect_image(70, 330, seed=100 + r, n_rect=8)
     ref = oracle.bilateral(f, r, 30.0, 30)
     out = _gpu_filter(f, r, 30.0, N=30, strip_h=23)
@@ -151,38 +151,39 @@ def test_compile_time_radius_kernels_multi_pass(r, N, sigma):
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
-@pytest.mark.parametrize("r,kc", [(7, 8), (7, 12), (7, 16), (7, 20), (7, 24),
-                                  (40, 8), (40, 12), (40, 16)])
+@pytest.mark.parametrize("r,kc", [(7, 8), (7, 12), (7, 16), (7, 20), (7, 24), (50, 20), (50, 24),
+                                  (70, 8), (70, 12), (70, 16)])
 def test_every_pass_size(kc, r):
     """30 folded orders (N = 59) in passes of 8, 12, 16, 20 or 24 orders (4, 3, 2, 2 or 2
     passes, the last one padded) against the oracle: every pass size of the compile-time
-    radius 7, and those of the run-time radius 40."""
+    radius 7, the large ones at the forward-only compile-time radius 50, and those of the
+    run-time radius 70 (256-lane strips)."""
     f = wl.rect_image(100, 300, seed=59, n_rect=10)
     ref = oracle.bilateral(f, r, 22.0, 59)
     out = _gpu_filter(f, r, 22.0, N=59, block=256, order_chunk=kc)
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
-@pytest.mark.parametrize("r", [5, 40])
+@pytest.mark.parametrize("r", [5, 70])
 def test_many_orders(r):
     """sigma_r = 10 (N_0 = 264, 133 folded orders): six 24-order passes at the compile-time
-    radius 5, nine 16-order ones at the run-time radius 40."""
+    radius 5, nine 16-order ones at the run-time radius 70."""
     f = wl.rect_image(48, 300, seed=264 + r, n_rect=8)
     N = order_for(10.0, T)
     ref = oracle.bilateral(f, r, 10.0, N)
-    out = _gpu_filter(f, r, 10.0, strip_h=17)
+    out = _gpu_filter(f, r, 10.0, strip_h=17, block=256)
     assert np.max(np.abs(out - ref)) <= TOL32
 
 
 @pytest.mark.parametrize("kc", [20, 24])
 def test_large_passes_need_a_compile_time_radius(kc):
-    """The 20- and 24-order passes exist at the radii 1 to 32 only; elsewhere the request is
-    rejected before any launch."""
+    """The 20- and 24-order passes exist at the compile-time radii (1 to 64) only; elsewhere
+    the request is rejected before any launch."""
     from paper_1107_4617_amd._lib import BskError
 
     f = wl.rect_image(40, 300, seed=1, n_rect=4)
     with pytest.raises(BskError, match="EINVAL"):
-        _gpu_filter(f, 40, 22.0, N=59, block=256, order_chunk=kc)
+        _gpu_filter(f, 70, 22.0, N=59, block=256, order_chunk=kc)
 
 
 @pytest.mark.parametrize("r,N", [(20, 43), (20, 44), (31, 43), (2, 44)])
