@@ -143,8 +143,8 @@ typedef struct {
  * Runs on the default stream and synchronises before returning.
  * Performance: with 256-lane strips (the default for r <= 64) every radius
  * from 1 to 64 runs kernels compiled for that radius in the plain FP32
- * forward, every radius from 1 to 32 in the training forward and adjoint
- * below, and the radii 3, 5,
+ * forward and the training forward below, every radius from 1 to 32 in the
+ * adjoint, and the radii 3, 5,
  * 8, 10, 16, 20, 25 and 32 also in the q_2 spatial kernel, the FP32
  * polynomial kernel and the two-pixel patch's 16-order pass.  They are 3-9%
  * faster than the run-time-radius kernels

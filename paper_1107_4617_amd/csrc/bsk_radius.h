@@ -1,5 +1,5 @@
-// The 256-lane plain FP32 forward (every radius 1 to 64, all that 256-lane
-// strips take by default), training forward and adjoint (radii 1 to 32) with
+// The 256-lane plain FP32 forward and training forward (every radius 1 to 64,
+// all that 256-lane strips take by default) and adjoint (radii 1 to 32) with
 // the box radius as a compile-time constant.  Their walkers
 // hand box sums to the R stage instead of prefix sums (strip_body, RHC > 0),
 // which halves the R stage's LDS reads: the forward's R stage reads four
@@ -7,9 +7,9 @@
 // Other radii, the 16-bit and compensated stacks use the run-time-radius
 // kernels of bsk_kernels.hip.
 //
-// The radii are compiled in parts of eight (bsk_radius_1_8.hip ...
-// bsk_radius_57_64.hip; the parts above 32 hold the forward only), so the build
-// compiles them in parallel; bsk_radius.hip picks the part.
+// The radii are compiled in eight parts of eight (bsk_radius_1_8.hip ...
+// bsk_radius_57_64.hip), so the build compiles them in parallel; bsk_radius.hip
+// picks the part.
 #pragma once
 #include <utility>
 
@@ -17,8 +17,10 @@
 
 namespace bsk {
 
-constexpr int kRadiusCtMax = 32;       // training forward and adjoint: radii 1 .. kRadiusCtMax
-constexpr int kRadiusCtMaxFwd = 64;    // forward: radii 1 .. kRadiusCtMaxFwd
+constexpr int kRadiusCtMax = 64;      // forward and training forward: radii 1 .. kRadiusCtMax
+// The adjoint's: above 32 the run-time-radius adjoint, with its one-pass
+// kernels' constant start mode, measured as fast (0.675 ms at r = 40, 4096^2).
+constexpr int kRadiusCtMaxBwd = 32;
 constexpr int kRadiusPerPart = 8;
 
 // One pass with the start mode as a constant (K <= KR), else passes with the
@@ -122,10 +124,14 @@ BSK_RADIUS_PART_DECL(9, 16)
 BSK_RADIUS_PART_DECL(17, 24)
 BSK_RADIUS_PART_DECL(25, 32)
 #undef BSK_RADIUS_PART_DECL
-// the forward-only parts (radii 33-40, 41-48, 49-56, 57-64)
-hipError_t forward_radius_33_40(const StripArgs &a, int kc, hipStream_t s, int *occ);
-hipError_t forward_radius_41_48(const StripArgs &a, int kc, hipStream_t s, int *occ);
-hipError_t forward_radius_49_56(const StripArgs &a, int kc, hipStream_t s, int *occ);
-hipError_t forward_radius_57_64(const StripArgs &a, int kc, hipStream_t s, int *occ);
+// forward and training forward only
+#define BSK_RADIUS_PART_DECL_FT(LO, HI)                                                                 \
+    hipError_t forward_radius_##LO##_##HI(const StripArgs &a, int kc, hipStream_t s, int *occ);          \
+    hipError_t train_radius_##LO##_##HI(const StripArgs &a, hipStream_t s, int *occ);
+BSK_RADIUS_PART_DECL_FT(33, 40)
+BSK_RADIUS_PART_DECL_FT(41, 48)
+BSK_RADIUS_PART_DECL_FT(49, 56)
+BSK_RADIUS_PART_DECL_FT(57, 64)
+#undef BSK_RADIUS_PART_DECL_FT
 
 }  // namespace bsk

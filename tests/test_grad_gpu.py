@@ -118,8 +118,9 @@ def test_rect4096_adjoint_sampled():
     assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(np.abs(ref))
 
 
-# Radii on both sides of the walker-chunk multiples and in each of the four compiled parts.
-CT_RADII = [1, 2, 3, 5, 7, 8, 10, 13, 16, 17, 20, 24, 25, 31, 32]
+# Radii on both sides of the walker-chunk multiples, in each compiled part up to 32, and above
+# 32 (compile-time training forward, run-time-radius adjoint).
+CT_RADII = [1, 2, 3, 5, 7, 8, 10, 13, 16, 17, 20, 24, 25, 31, 32, 40, 57, 64]
 
 
 @pytest.mark.parametrize("r", CT_RADII)
@@ -145,12 +146,12 @@ def test_compile_time_radius_gradients(r, N, sigma):
     assert abs(float(gs) - gs_ref) <= 1e-3 * abs(gs_ref)
 
 
-@pytest.mark.parametrize("r", [0, 33, 47])
+@pytest.mark.parametrize("r", [0, 70])
 @pytest.mark.parametrize("N,sigma", [(30, 30.0), (31, 30.0), (43, 25.0), (42, 25.0), (7, 70.0)])
 def test_run_time_radius_gradients(r, N, sigma):
-    """256-lane strips at radii without compile-time-radius kernels (0 and above 32): the
-    one-pass 16- and 24-order adjoints with the start mode as a constant, both modes, and
-    the half pass, against the oracle."""
+    """Radii without compile-time-radius kernels: 0 (256-lane strips: the one-pass 16- and
+    24-order adjoints with the start mode as a constant, both modes, and the half pass) and
+    70 (512-lane strips), against the oracle."""
     f = wl.rect_image(36, 300, seed=7 * r + N, n_rect=8)
     g = np.random.default_rng(r + 2 * N).normal(size=f.shape)
     gf_ref, gs_ref, u_ref = oracle.bilateral_grad(f.astype(np.float64), g, r, sigma, N)
