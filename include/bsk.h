@@ -144,12 +144,10 @@ typedef struct {
  * Performance: with 256-lane strips (the default for r <= 64) every radius
  * from 1 to 64 runs kernels compiled for that radius in the plain FP32
  * forward and the training forward below, every radius from 1 to 32 in the
- * adjoint, and the radii 3, 5,
- * 8, 10, 16, 20, 25 and 32 also in the q_2 spatial kernel, the FP32
- * polynomial kernel and the two-pixel patch's 16-order pass.  They are 3-9%
- * faster than the run-time-radius kernels
- * the other radii use (the adjoint about 25%); the results agree to FP32
- * rounding.
+ * adjoint, and the radii 3, 5, 8, 10, 16, 20, 25 and 32 also in the q_2
+ * spatial kernel, the FP32 polynomial kernel and the two-pixel patch's
+ * 16-order pass.  They are 3-10% faster than the run-time-radius kernels the
+ * other radii use; the results agree to FP32 rounding.
  */
 int bilateral_shiftable(const float *img, int H, int W, int radius, float sigma_r, float T,
                         float *out);
