@@ -60,7 +60,7 @@ typedef enum {
     BSK_ERANGE = -2,        /* order too large (more than BSK_MAX_ORDERS folded orders) */
     BSK_ENOMEM = -3,        /* workspace allocation failed */
     BSK_EHIP = -4,          /* HIP runtime error (no device, launch failure, ...) */
-    BSK_EUNSUPPORTED = -5   /* valid request this build does not handle */
+    BSK_EUNSUPPORTED = -5   /* valid request the library does not handle */
 } bsk_status;
 
 typedef enum {
